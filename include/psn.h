@@ -1,0 +1,143 @@
+/*
+ * psn.h -- C ABI of the MI355X free-space Poisson solver.
+ *
+ * Computes u = U * rho with U(x) = 1/(4 pi |x|) on a cube [-L, L]^3 sampled
+ * with n points per axis (both end points included, h = 2L/(n-1)), by the
+ * method of Exl, "A GPU accelerated and error-controlled solver for the
+ * unbounded Poisson equation in three dimensions" (arXiv 1612.01799):
+ *
+ *   u = crop( IFFT_2n( K * FFT_2n( pad(rho) ) ) ),
+ *
+ * where K is the spectrum of the Gaussian-sum approximation of U truncated to
+ * [-T, T]^3 (T = n h) plus the symbol C0 - (C2/6)|kappa|^2 of the near-zone
+ * correction (paper section 2, eq. approx and the G-tensor; section 3 for the
+ * transform sizes).  The solve is five pruned passes over the padded (2n)^3
+ * spectrum that never materialise its zero half.
+ *
+ * Conventions shared by every entry point
+ *   - Arrays are C order [i0][i1][i2] (i2 contiguous) of n^3 reals.
+ *   - rho and u are DEVICE pointers owned by the caller.  F32 plans read and
+ *     write float; F64 and SPLIT plans read and write double.
+ *   - `stream` is a hipStream_t (NULL = the legacy default stream).  Solves are
+ *     enqueued asynchronously and stream-ordered; argument and state errors are
+ *     returned synchronously before anything is enqueued.
+ *   - No function throws; every failure is a psn_status.
+ */
+#ifndef PSN_H
+#define PSN_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct psn_plan psn_plan;
+
+/* Arithmetic of a plan.
+ *   PSN_F64   FP64 arithmetic and FP64 storage everywhere.
+ *   PSN_F32   FP32 arithmetic, FP32 storage, FP32 kernel spectrum.
+ *   PSN_SPLIT FP64 arithmetic inside each pass; intermediates between passes
+ *             stored as an FP32 high part plus a bfloat16 low part (6 bytes per
+ *             real); FP64 kernel spectrum; FP64 input and output. */
+typedef enum { PSN_F64 = 0, PSN_F32 = 1, PSN_SPLIT = 2 } psn_dtype;
+
+typedef enum {
+    PSN_OK = 0,
+    PSN_EINVAL = -1,  /* bad argument: null pointer, L <= 0, tol outside [1e-15, 1e-4], bad dtype */
+    PSN_ESIZE = -2,   /* n not supported: n must be even, 2n = 2^a 3^b 5^c, and compiled in */
+    PSN_ENOMEM = -3,  /* device allocation failed */
+    PSN_EDEVICE = -4, /* a HIP call or kernel launch failed */
+    PSN_ESTATE = -5,  /* psn_solve before psn_kernel_build */
+    PSN_EFIT = -6     /* the Gaussian-sum fit missed tol on [delta, R] */
+} psn_status;
+
+typedef struct {
+    int n;              /* points per axis */
+    int dtype;          /* psn_dtype */
+    double L;           /* half-width of the cube */
+    double tol;         /* requested Gaussian-sum relative tolerance eps */
+    double h;           /* grid spacing 2L/(n-1) */
+    double T;           /* kernel truncation n*h (half the padded period) */
+    double period;      /* padded FFT period 2*n*h */
+    double delta;       /* near-zone radius (section 3 heuristic, physical units) */
+    double R;           /* largest distance the Gaussian sum must resolve: 2*sqrt(3)*L */
+    double hs;          /* sinc-quadrature step */
+    int terms;          /* number of Gaussian-sum terms (S + 1) */
+    double eps_achieved;/* max |U_GS/U - 1| on the check grid */
+    double C0, C2;      /* correction constants; valid once built */
+    int built;          /* 1 after psn_kernel_build succeeded */
+    size_t device_bytes;     /* device memory held by the plan */
+    double algorithmic_bytes;/* HBM bytes one solve must move (five pruned passes) */
+} psn_plan_info;
+
+/* Create a plan for an n^3 grid on [-L, L]^3 (the solver construction of the
+ * paper's section 4; setup is kept apart from solves, section 3).  Host only:
+ * computes the geometry, the near-zone radius and the Gaussian-sum table, and
+ * checks that table against 1/(4 pi r) on [delta, R] to `tol`.  No device work
+ * and no device memory.  On success *out owns a new plan; on failure *out is
+ * set to NULL.  Errors: PSN_EINVAL, PSN_ESIZE, PSN_EFIT. */
+psn_status psn_plan_create(int n, double L, double tol, psn_dtype dtype, psn_plan **out);
+
+/* Build the kernel spectrum on the current device (the G-tensor precomputation
+ * of section 3): FP64 mode integrals, correction constants C0 and C2 and the
+ * octant assembly, then conversion to the plan's storage type; also allocates
+ * the solve workspace.  Synchronises `stream` before returning.  Idempotent.
+ * Errors: PSN_EINVAL, PSN_ENOMEM, PSN_EDEVICE. */
+psn_status psn_kernel_build(psn_plan *p, void *stream);
+
+/* Enqueue one solve u = U * rho (paper eq. conv, approximated as in eq.
+ * approx).  rho and u are device arrays of n^3 elements of the plan's I/O
+ * type; rho == u is allowed.  The plan's workspace is shared, so calls on one
+ * plan must not overlap across streams.
+ * Errors: PSN_EINVAL, PSN_ESTATE, PSN_EDEVICE. */
+psn_status psn_solve(psn_plan *p, const void *rho, void *u, void *stream);
+
+/* Enqueue `count` independent solves, possibly of different sizes, as one
+ * batch (many densities on one device).  plans[i], rho[i], u[i] as for
+ * psn_solve; the same plan may appear more than once (its solves are then
+ * ordered on the stream).  Errors: as psn_solve, for the first bad entry. */
+psn_status psn_solve_batched(int count, psn_plan *const *plans,
+                             const void *const *rho, void *const *u, void *stream);
+
+/* As psn_solve, but also records a HIP event on `stream` before the first
+ * pass and after each of the five passes (P1 axis-2 real-to-complex, P2
+ * axis-1 forward, P3 axis-0 forward x K inverse, P4 axis-1 inverse, P5 axis-2
+ * complex-to-real), waits for the stream, and writes the five pass durations
+ * in milliseconds to pass_ms[5].  For measurement only (it synchronises).
+ * Errors: as psn_solve. */
+psn_status psn_solve_timed(psn_plan *p, const void *rho, void *u, void *stream, double *pass_ms);
+
+/* Fill *info.  Errors: PSN_EINVAL. */
+psn_status psn_plan_query(const psn_plan *p, psn_plan_info *info);
+
+/* Copy the Gaussian-sum table to host arrays tau[cap], w[cap] (section 2:
+ * U_GS(r) = sum_j w_j exp(-tau_j^2 r^2)).  Returns the number of terms in
+ * *terms; copies min(cap, terms) entries.  Errors: PSN_EINVAL. */
+psn_status psn_plan_gs_table(const psn_plan *p, double *tau, double *w, int cap, int *terms);
+
+/* Copy the built kernel spectrum to a host array octant[(n+1)^3], FP64, index
+ * [k0][k1][k2] with k_q = 0..n the folded frequency index, in the paper's
+ * normalisation (no 1/(2n)^3 factor).  Synchronous.
+ * Errors: PSN_EINVAL, PSN_ESTATE, PSN_EDEVICE. */
+psn_status psn_kernel_download(const psn_plan *p, double *octant);
+
+/* Release the plan and its device memory.  NULL is a no-op. */
+void psn_plan_destroy(psn_plan *p);
+
+/* Text of the last HIP failure seen by this library on the calling thread
+ * (the failing call and HIP's message), or "" if there was none.  The
+ * string stays valid until the next call into the library on this thread. */
+const char *psn_last_error(void);
+
+/* Static description of a status code. */
+const char *psn_strerror(psn_status st);
+
+/* Nonzero if n is a supported grid size (even, 2n 5-smooth, compiled in). */
+int psn_size_supported(int n);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PSN_H */

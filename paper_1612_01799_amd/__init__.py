@@ -1,0 +1,209 @@
+"""MI355X free-space Poisson solver: thin Python binding of ``libpsn.so``.
+
+Every step of a solve runs in the HIP kernels of the C library; this module
+only marshals arguments (plan handles, device pointers, the current HIP
+stream).  PyTorch supplies device memory and streams.  There is no fallback:
+if the library is missing, importing this module raises ImportError.
+
+    import torch, paper_1612_01799_amd as psn
+    plan = psn.Plan(n=128, L=8.0, tol=1e-12, dtype="f32").build()
+    u = plan.solve(rho)            # rho: (n, n, n) float32 CUDA tensor
+
+The names follow the C ABI in ``include/psn.h``: ``plan_create``,
+``kernel_build``, ``solve``, ``solve_batched``, ``plan_query``.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+__all__ = ["Plan", "PsnError", "solve_batched", "size_supported", "library_path",
+           "F64", "F32", "SPLIT", "STATUS"]
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "libpsn.so")
+
+F64, F32, SPLIT = 0, 1, 2
+_DTYPES = {"f64": F64, "f32": F32, "split": SPLIT, F64: F64, F32: F32, SPLIT: SPLIT}
+STATUS = {0: "PSN_OK", -1: "PSN_EINVAL", -2: "PSN_ESIZE", -3: "PSN_ENOMEM", -4: "PSN_EDEVICE",
+          -5: "PSN_ESTATE", -6: "PSN_EFIT"}
+
+
+class PsnError(RuntimeError):
+    def __init__(self, status: int, what: str):
+        self.status = status
+        detail = _lib.psn_last_error().decode()
+        msg = f"{what}: {STATUS.get(status, status)} ({_lib.psn_strerror(status).decode()})"
+        super().__init__(msg + (f"; {detail}" if detail else ""))
+
+
+class PlanInfo(ctypes.Structure):
+    _fields_ = [
+        ("n", ctypes.c_int), ("dtype", ctypes.c_int), ("L", ctypes.c_double), ("tol", ctypes.c_double),
+        ("h", ctypes.c_double), ("T", ctypes.c_double), ("period", ctypes.c_double),
+        ("delta", ctypes.c_double), ("R", ctypes.c_double), ("hs", ctypes.c_double),
+        ("terms", ctypes.c_int), ("eps_achieved", ctypes.c_double), ("C0", ctypes.c_double),
+        ("C2", ctypes.c_double), ("built", ctypes.c_int), ("device_bytes", ctypes.c_size_t),
+        ("algorithmic_bytes", ctypes.c_double),
+    ]
+
+
+def _load():
+    # One HIP runtime per process: torch ships its own libamdhip64 (soname
+    # libamdhip64.so.7) and loads it by an unversioned name, so if this library
+    # were loaded first the process would end up with two runtimes and the
+    # second would see no device.  Loading torch first makes the library bind
+    # to torch's runtime through the shared soname.
+    import torch  # noqa: F401
+    if not os.path.exists(_LIB_PATH):
+        raise ImportError(f"{_LIB_PATH} is not built; run `python paper_1612_01799_amd/build.py`")
+    lib = ctypes.CDLL(_LIB_PATH)
+    P = ctypes.c_void_p
+    sig = {
+        "psn_plan_create": (ctypes.c_int, [ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_int,
+                                           ctypes.POINTER(P)]),
+        "psn_kernel_build": (ctypes.c_int, [P, P]),
+        "psn_solve": (ctypes.c_int, [P, P, P, P]),
+        "psn_solve_timed": (ctypes.c_int, [P, P, P, P, ctypes.POINTER(ctypes.c_double)]),
+        "psn_solve_batched": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(P), ctypes.POINTER(P),
+                                             ctypes.POINTER(P), P]),
+        "psn_plan_query": (ctypes.c_int, [P, ctypes.POINTER(PlanInfo)]),
+        "psn_plan_gs_table": (ctypes.c_int, [P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
+                                             ctypes.c_int, ctypes.POINTER(ctypes.c_int)]),
+        "psn_kernel_download": (ctypes.c_int, [P, ctypes.POINTER(ctypes.c_double)]),
+        "psn_plan_destroy": (None, [P]),
+        "psn_strerror": (ctypes.c_char_p, [ctypes.c_int]),
+        "psn_last_error": (ctypes.c_char_p, []),
+        "psn_size_supported": (ctypes.c_int, [ctypes.c_int]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    return lib
+
+
+_lib = _load()
+
+
+def library_path() -> str:
+    return _LIB_PATH
+
+
+def size_supported(n: int) -> bool:
+    return bool(_lib.psn_size_supported(int(n)))
+
+
+def _check(st: int, what: str):
+    if st != 0:
+        raise PsnError(st, what)
+
+
+def _stream_handle(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(int(stream.cuda_stream))
+
+
+class Plan:
+    """One grid geometry: n^3 points on [-L, L]^3, Gaussian-sum tolerance tol."""
+
+    def __init__(self, n: int, L: float, tol: float = 1e-12, dtype="f32"):
+        self._h = ctypes.c_void_p()
+        self.n = int(n)
+        self.L = float(L)
+        self.dtype = _DTYPES[dtype]
+        _check(_lib.psn_plan_create(self.n, self.L, float(tol), self.dtype, ctypes.byref(self._h)),
+               "psn_plan_create")
+
+    # -- setup
+    def build(self, stream=None) -> "Plan":
+        _check(_lib.psn_kernel_build(self._h, _stream_handle(stream)), "psn_kernel_build")
+        return self
+
+    # -- solve
+    def io_dtype(self):
+        import torch
+        return torch.float32 if self.dtype == F32 else torch.float64
+
+    def solve(self, rho, out=None, stream=None):
+        import torch
+        n = self.n
+        if rho.shape != (n, n, n) or rho.dtype != self.io_dtype() or not rho.is_cuda or not rho.is_contiguous():
+            raise ValueError(f"rho must be a contiguous ({n},{n},{n}) {self.io_dtype()} CUDA tensor")
+        if out is None:
+            out = torch.empty_like(rho)
+        elif out.shape != rho.shape or out.dtype != rho.dtype or not out.is_contiguous():
+            raise ValueError("out must match rho")
+        _check(_lib.psn_solve(self._h, ctypes.c_void_p(rho.data_ptr()), ctypes.c_void_p(out.data_ptr()),
+                              _stream_handle(stream)), "psn_solve")
+        return out
+
+    def solve_timed(self, rho, out, stream=None):
+        """One solve with per-pass HIP events; returns the five pass times in ms."""
+        import numpy as np
+        ms = np.zeros(5)
+        _check(_lib.psn_solve_timed(self._h, ctypes.c_void_p(rho.data_ptr()), ctypes.c_void_p(out.data_ptr()),
+                                    _stream_handle(stream), ms.ctypes.data_as(ctypes.POINTER(ctypes.c_double))),
+               "psn_solve_timed")
+        return ms
+
+    # -- introspection
+    def info(self) -> dict:
+        inf = PlanInfo()
+        _check(_lib.psn_plan_query(self._h, ctypes.byref(inf)), "psn_plan_query")
+        return {f: getattr(inf, f) for f, _ in PlanInfo._fields_}
+
+    def gs_table(self):
+        import numpy as np
+        m = ctypes.c_int()
+        _check(_lib.psn_plan_gs_table(self._h, None, None, 0, ctypes.byref(m)), "psn_plan_gs_table")
+        tau = np.empty(m.value)
+        w = np.empty(m.value)
+        dp = ctypes.POINTER(ctypes.c_double)
+        _check(_lib.psn_plan_gs_table(self._h, tau.ctypes.data_as(dp), w.ctypes.data_as(dp), m.value,
+                                      ctypes.byref(m)), "psn_plan_gs_table")
+        return tau, w
+
+    def kernel_octant(self):
+        import numpy as np
+        k = np.empty((self.n + 1,) * 3)
+        _check(_lib.psn_kernel_download(self._h, k.ctypes.data_as(ctypes.POINTER(ctypes.c_double))),
+               "psn_kernel_download")
+        return k
+
+    @property
+    def handle(self):
+        return self._h
+
+    def close(self):
+        if self._h:
+            _lib.psn_plan_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def solve_batched(plans, rhos, outs=None, stream=None):
+    """Enqueue one batch of solves (sizes may differ); returns the outputs."""
+    import torch
+    count = len(plans)
+    if len(rhos) != count:
+        raise ValueError("plans and rhos differ in length")
+    if outs is None:
+        outs = [torch.empty_like(r) for r in rhos]
+    for p, r, o in zip(plans, rhos, outs):
+        n = p.n
+        if r.shape != (n, n, n) or r.dtype != p.io_dtype() or not r.is_contiguous() or o.shape != r.shape:
+            raise ValueError("batch entry does not match its plan")
+    P = ctypes.c_void_p
+    hp = (P * count)(*[p.handle for p in plans])
+    hr = (P * count)(*[P(r.data_ptr()) for r in rhos])
+    ho = (P * count)(*[P(o.data_ptr()) for o in outs])
+    _check(_lib.psn_solve_batched(count, hp, hr, ho, _stream_handle(stream)), "psn_solve_batched")
+    return outs

@@ -1,0 +1,359 @@
+// Device building blocks for the pruned padded-FFT convolution on gfx950:
+// complex arithmetic, in-register DFT butterflies, the register-resident
+// Stockham "team" FFT, and the storage formats of the three precisions.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace psn {
+
+// ----------------------------------------------------------------- complex
+template <class R>
+struct cx {
+    R x, y;
+};
+
+template <class R>
+__device__ __forceinline__ cx<R> operator+(cx<R> a, cx<R> b) { return {a.x + b.x, a.y + b.y}; }
+template <class R>
+__device__ __forceinline__ cx<R> operator-(cx<R> a, cx<R> b) { return {a.x - b.x, a.y - b.y}; }
+template <class R>
+__device__ __forceinline__ cx<R> operator*(cx<R> a, cx<R> b) {
+    return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
+template <class R>
+__device__ __forceinline__ cx<R> scale(cx<R> a, R s) { return {a.x * s, a.y * s}; }
+template <class R>
+__device__ __forceinline__ cx<R> conj(cx<R> a) { return {a.x, -a.y}; }
+// a * conj(w)
+template <class R>
+__device__ __forceinline__ cx<R> mul_conj(cx<R> a, cx<R> w) {
+    return {a.x * w.x + a.y * w.y, a.y * w.x - a.x * w.y};
+}
+// multiply by DIR * i  (DIR = -1 forward, +1 inverse)
+template <int DIR, class R>
+__device__ __forceinline__ cx<R> rot(cx<R> a) {
+    if constexpr (DIR < 0) return {a.y, -a.x};
+    else return {-a.y, a.x};
+}
+// twiddle product: a * w (forward) or a * conj(w) (inverse)
+template <int DIR, class R>
+__device__ __forceinline__ cx<R> twmul(cx<R> a, cx<R> w) {
+    if constexpr (DIR < 0) return a * w;
+    else return mul_conj(a, w);
+}
+
+// ----------------------------------------------------------------- butterflies
+// In-register DFT of length R with sign DIR: v[k] <- sum_j v[j] exp(DIR 2 pi i jk/R).
+template <int R, int DIR, class T>
+struct DFT;
+
+template <int DIR, class T>
+struct DFT<2, DIR, T> {
+    static __device__ __forceinline__ void run(cx<T>* v) {
+        cx<T> a = v[0];
+        v[0] = a + v[1];
+        v[1] = a - v[1];
+    }
+};
+
+template <int DIR, class T>
+struct DFT<4, DIR, T> {
+    static __device__ __forceinline__ void run(cx<T>* v) {
+        cx<T> t0 = v[0] + v[2], t1 = v[0] - v[2];
+        cx<T> t2 = v[1] + v[3], t3 = rot<DIR>(v[1] - v[3]);
+        v[0] = t0 + t2;
+        v[2] = t0 - t2;
+        v[1] = t1 + t3;
+        v[3] = t1 - t3;
+    }
+};
+
+template <int DIR, class T>
+struct DFT<3, DIR, T> {
+    static __device__ __forceinline__ void run(cx<T>* v) {
+        const T h = T(0.86602540378443864676);  // sin(2 pi / 3)
+        cx<T> t1 = v[1] + v[2], t2 = v[1] - v[2];
+        cx<T> m = v[0] - scale(t1, T(0.5));
+        cx<T> s = rot<DIR>(scale(t2, h));
+        v[0] = v[0] + t1;
+        v[1] = m + s;
+        v[2] = m - s;
+    }
+};
+
+template <int DIR, class T>
+struct DFT<5, DIR, T> {
+    static __device__ __forceinline__ void run(cx<T>* v) {
+        const T c1 = T(0.30901699437494742410), c2 = T(-0.80901699437494742410);
+        const T s1 = T(0.95105651629515357212), s2 = T(0.58778525229247312917);
+        cx<T> t1 = v[1] + v[4], t2 = v[2] + v[3], t3 = v[1] - v[4], t4 = v[2] - v[3];
+        cx<T> a1 = v[0] + scale(t1, c1) + scale(t2, c2);
+        cx<T> a2 = v[0] + scale(t1, c2) + scale(t2, c1);
+        cx<T> b1 = rot<DIR>(scale(t3, s1) + scale(t4, s2));
+        cx<T> b2 = rot<DIR>(scale(t3, s2) - scale(t4, s1));
+        v[0] = v[0] + t1 + t2;
+        v[1] = a1 + b1;
+        v[4] = a1 - b1;
+        v[2] = a2 + b2;
+        v[3] = a2 - b2;
+    }
+};
+
+template <int DIR, class T>
+struct DFT<8, DIR, T> {
+    static __device__ __forceinline__ void run(cx<T>* v) {
+        const T q = T(0.70710678118654752440);
+        cx<T> a[4] = {v[0], v[2], v[4], v[6]};
+        cx<T> b[4] = {v[1], v[3], v[5], v[7]};
+        DFT<4, DIR, T>::run(a);
+        DFT<4, DIR, T>::run(b);
+        // b[k] *= exp(DIR 2 pi i k / 8)
+        b[1] = {q * (b[1].x - DIR * b[1].y), q * (b[1].y + DIR * b[1].x)};
+        b[2] = rot<DIR>(b[2]);
+        b[3] = {q * (-b[3].x - DIR * b[3].y), q * (-b[3].y + DIR * b[3].x)};
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            v[k] = a[k] + b[k];
+            v[k + 4] = a[k] - b[k];
+        }
+    }
+};
+
+template <int DIR, class T>
+struct DFT<16, DIR, T> {
+    static __device__ __forceinline__ void run(cx<T>* v) {
+        const T c = T(0.92387953251128675613), s = T(0.38268343236508977173);
+        const T q = T(0.70710678118654752440);
+        cx<T> a[4][4];
+#pragma unroll
+        for (int j0 = 0; j0 < 4; ++j0) {
+#pragma unroll
+            for (int j1 = 0; j1 < 4; ++j1) a[j0][j1] = v[j0 + 4 * j1];
+            DFT<4, DIR, T>::run(a[j0]);
+        }
+        // a[j0][k1] *= exp(DIR 2 pi i j0 k1 / 16); the exponent j0*k1 is in {0..9}
+        const T cs[10] = {T(1), c, q, s, T(0), -s, -q, -c, T(-1), -c};
+        const T sn[10] = {T(0), s, q, c, T(1), c, q, s, T(0), -s};
+#pragma unroll
+        for (int j0 = 1; j0 < 4; ++j0) {
+#pragma unroll
+            for (int k1 = 1; k1 < 4; ++k1) {
+                const int e = j0 * k1;
+                const cx<T> w = {cs[e], T(DIR) * sn[e]};
+                a[j0][k1] = a[j0][k1] * w;
+            }
+        }
+#pragma unroll
+        for (int k1 = 0; k1 < 4; ++k1) {
+            cx<T> b[4] = {a[0][k1], a[1][k1], a[2][k1], a[3][k1]};
+            DFT<4, DIR, T>::run(b);
+#pragma unroll
+            for (int k0 = 0; k0 < 4; ++k0) v[k1 + 4 * k0] = b[k0];
+        }
+    }
+};
+
+// ----------------------------------------------------------------- radix plan
+struct RadixPlan {
+    int n;
+    int r[16];
+};
+
+// Stages for a length-N transform with E elements per thread: odd radices
+// first, then the largest power-of-two radix (<= 16) dividing both what is
+// left of N and the power-of-two part of E, so each stage gives every thread
+// a whole number of butterflies.
+constexpr RadixPlan make_plan(int N, int E) {
+    RadixPlan p{0, {}};
+    int rem = N;
+    while (rem % 5 == 0) { p.r[p.n++] = 5; rem /= 5; }
+    while (rem % 3 == 0) { p.r[p.n++] = 3; rem /= 3; }
+    int e2 = E & -E;
+    while (rem > 1) {
+        int R = 16;
+        while (R > 1 && (rem % R != 0 || e2 % R != 0)) R /= 2;
+        if (R == 1) return RadixPlan{-1, {}};
+        p.r[p.n++] = R;
+        rem /= R;
+    }
+    return p;
+}
+
+// Elements per thread for a length-N line: all of N's odd factors times up to
+// 16 (N a power of two) or 4 (N with a factor 3 or 5) of its powers of two.
+constexpr int elems_per_thread(int N) {
+    int odd = N;
+    while (odd % 2 == 0) odd /= 2;
+    int p2 = N / odd;
+    int cap = odd == 1 ? 16 : 4;
+    return odd * (p2 < cap ? p2 : cap);
+}
+
+// ----------------------------------------------------------------- team FFT
+// A team of T threads computes one length-N transform (DIR = -1 forward,
+// +1 inverse, unnormalised) with the Stockham autosort algorithm: natural
+// order in and out.  Thread t holds E = N/T elements in registers.  On entry
+// slot e holds input position in_pos(t, e); on exit it holds output position
+// out_pos(t, e).  Between stages the team exchanges through an LDS view
+// (`Lds::put/get` at a position, `Lds::sync` = workgroup barrier).
+// With REV the radices run in reverse order; a REV transform's in_pos is the
+// forward transform's out_pos, so a forward pass and a REV inverse pass can be
+// chained in registers (used for the fused multiply of the middle pass).
+template <int N, int T, class Real, int DIR, bool REV>
+struct TeamFFT {
+    static constexpr int E = N / T;
+    static constexpr RadixPlan plan = make_plan(N, E);
+    static constexpr int S = plan.n;
+    static_assert(N % T == 0, "team must divide the line");
+    static_assert(S > 0, "no radix plan for this size");
+
+    static constexpr int radix(int i) { return REV ? plan.r[S - 1 - i] : plan.r[i]; }
+    static constexpr int span(int i) {
+        int ns = 1;
+        for (int q = 0; q < i; ++q) ns *= radix(q);
+        return ns;
+    }
+    static constexpr int R0 = radix(0);
+    static constexpr int RL = radix(S - 1);
+
+    static __device__ __forceinline__ int in_pos(int t, int e) {
+        return t + T * (e / R0) + (e % R0) * (N / R0);
+    }
+    static __device__ __forceinline__ int out_pos(int t, int e) {
+        return t + T * (e / RL) + (e % RL) * (N / RL);
+    }
+
+    template <int I, class Lds>
+    static __device__ __forceinline__ void stage(cx<Real> (&d)[E], int t, const cx<Real>* __restrict__ tw,
+                                                 Lds& lds) {
+        if constexpr (I < S) {
+            constexpr int R = radix(I);
+            constexpr int Ns = span(I);
+            constexpr int twstep = 2 * N / (Ns * R);  // table has 2N entries: exp(-2 pi i m / 2N)
+            if constexpr (I > 0) {
+#pragma unroll
+                for (int e = 0; e < E; ++e) d[e] = lds.get(t + T * (e / R) + (e % R) * (N / R));
+            }
+#pragma unroll
+            for (int s = 0; s < E / R; ++s) {
+                cx<Real>* v = d + s * R;
+                if constexpr (Ns > 1) {
+                    const int k = (t + T * s) % Ns;
+#pragma unroll
+                    for (int r = 1; r < R; ++r) v[r] = twmul<DIR>(v[r], tw[r * k * twstep]);
+                }
+                DFT<R, DIR, Real>::run(v);
+            }
+            if constexpr (I + 1 < S) {
+                lds.sync();
+#pragma unroll
+                for (int e = 0; e < E; ++e) {
+                    const int b = t + T * (e / R);
+                    lds.put((b / Ns) * Ns * R + (b % Ns) + (e % R) * Ns, d[e]);
+                }
+                lds.sync();
+            }
+            stage<I + 1>(d, t, tw, lds);
+        }
+    }
+
+    template <class Lds>
+    static __device__ __forceinline__ void run(cx<Real> (&d)[E], int t, const cx<Real>* __restrict__ tw,
+                                               Lds& lds) {
+        stage<0>(d, t, tw, lds);
+    }
+};
+
+// ----------------------------------------------------------------- LDS views
+// Strided passes: lines are columns of a tile, element-major, column fastest.
+template <class Real>
+struct LdsCols {
+    cx<Real>* buf;
+    int stride;  // columns per element row
+    int col;
+    __device__ __forceinline__ void put(int pos, cx<Real> v) { buf[pos * stride + col] = v; }
+    __device__ __forceinline__ cx<Real> get(int pos) const { return buf[pos * stride + col]; }
+    __device__ __forceinline__ void sync() { __syncthreads(); }
+};
+
+// Contiguous passes: one row per line, with one pad slot every 16 elements so
+// strided butterfly writes spread over the banks.
+template <class Real>
+struct LdsRows {
+    cx<Real>* buf;
+    __device__ __forceinline__ static int skew(int pos) { return pos + (pos >> 4); }
+    __device__ __forceinline__ void put(int pos, cx<Real> v) { buf[skew(pos)] = v; }
+    __device__ __forceinline__ cx<Real> get(int pos) const { return buf[skew(pos)]; }
+    __device__ __forceinline__ void sync() { __syncthreads(); }
+};
+
+// ----------------------------------------------------------------- storage
+// Precision codes match psn_dtype.
+enum { DT_F64 = 0, DT_F32 = 1, DT_SPLIT = 2 };
+
+template <int DT>
+struct Prec;
+
+template <>
+struct Prec<DT_F64> {
+    using Real = double;  // arithmetic
+    using Io = double;    // rho, u
+    using Kt = double;    // kernel spectrum
+};
+template <>
+struct Prec<DT_F32> {
+    using Real = float;
+    using Io = float;
+    using Kt = float;
+};
+template <>
+struct Prec<DT_SPLIT> {
+    using Real = double;
+    using Io = double;
+    using Kt = double;
+};
+
+__device__ __forceinline__ uint32_t f32_to_bf16_rne(float f) {
+    uint32_t u = __float_as_uint(f);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return u >> 16;
+}
+__device__ __forceinline__ float bf16_to_f32(uint32_t b) { return __uint_as_float(b << 16); }
+
+// Workspace of complex values between passes.
+template <int DT>
+struct Work;
+
+template <>
+struct Work<DT_F32> {
+    cx<float>* p;
+    __device__ __forceinline__ cx<float> ld(size_t i) const { return p[i]; }
+    __device__ __forceinline__ void st(size_t i, cx<float> v) const { p[i] = v; }
+};
+template <>
+struct Work<DT_F64> {
+    cx<double>* p;
+    __device__ __forceinline__ cx<double> ld(size_t i) const { return p[i]; }
+    __device__ __forceinline__ void st(size_t i, cx<double> v) const { p[i] = v; }
+};
+// FP32 high part + bfloat16 low part (two per 32-bit word): 6 bytes per real.
+template <>
+struct Work<DT_SPLIT> {
+    cx<float>* hi;
+    uint32_t* lo;
+    __device__ __forceinline__ cx<double> ld(size_t i) const {
+        cx<float> h = hi[i];
+        uint32_t l = lo[i];
+        return {double(h.x) + double(bf16_to_f32(l & 0xFFFFu)), double(h.y) + double(bf16_to_f32(l >> 16))};
+    }
+    __device__ __forceinline__ void st(size_t i, cx<double> v) const {
+        float hx = float(v.x), hy = float(v.y);
+        float lx = float(v.x - double(hx)), ly = float(v.y - double(hy));
+        hi[i] = {hx, hy};
+        lo[i] = f32_to_bf16_rne(lx) | (f32_to_bf16_rne(ly) << 16);
+    }
+};
+
+}  // namespace psn

@@ -1,0 +1,57 @@
+// Host-side plan state shared by the ABI layer and the kernel launchers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <vector>
+
+#include "../../include/psn.h"
+
+// Grid sizes compiled into the library: even n with 2n = 2^a 3^b 5^c.
+#define PSN_FOR_EACH_SIZE(X) \
+    X(8) X(12) X(16) X(24) X(32) X(48) X(64) X(96) X(128) X(160) X(192) X(256) X(320) X(384) X(512)
+
+struct psn_plan {
+    // geometry (section 4 grid; padded period 2nh; truncation T = nh)
+    int n = 0;
+    double L = 0, tol = 0;
+    psn_dtype dtype = PSN_F64;
+    double h = 0, T = 0, period = 0, delta = 0, R = 0;
+    // Gaussian sum (section 2)
+    double hs = 0, gs_err = 0;
+    std::vector<double> tau, w;
+    // device state
+    int device = -1;
+    bool built = false;
+    double C0 = 0, C2 = 0;
+    void* K = nullptr;    // [k1~][k0~][k2] k1~,k0~ in 0..n, k2 in 0..n-1 (column 0 holds (K0+Kn)/2)
+    void* Kb = nullptr;   // [k1~][k0~] (K0-Kn)/2 for the packed DC/Nyquist column
+    void* tw = nullptr;   // 2n twiddles exp(-2 pi i m / 2n), compute precision
+    void* W1 = nullptr;   // n * n * n complex
+    void* W2 = nullptr;   // n * 2n * n complex
+    void* W1lo = nullptr; // SPLIT low parts
+    void* W2lo = nullptr;
+    size_t device_bytes = 0;
+};
+
+namespace psn_host {
+
+// One solve: five passes enqueued on `stream`.  Returns hipSuccess or the
+// launch error.
+// With `ev` non-null, ev[0] is recorded before the first pass and ev[i] after
+// pass i (i = 1..5).
+hipError_t launch_solve(const psn_plan* p, const void* rho, void* u, hipStream_t stream,
+                        hipEvent_t* ev = nullptr);
+
+// Kernel spectrum build on the device (FP64), written into p->K / p->Kb in
+// the plan's storage type, plus C0/C2 into the two doubles at d_c.
+hipError_t launch_kernel_build(psn_plan* p, const double* d_tau, const double* d_w, int terms,
+                               const double* d_glx, const double* d_glw, double* d_A, double* d_c,
+                               hipStream_t stream);
+
+size_t elem_bytes(psn_dtype dt);        // bytes of one complex intermediate in the main array
+size_t kernel_elem_bytes(psn_dtype dt); // bytes of one real of the kernel spectrum
+bool size_compiled(int n);
+
+}  // namespace psn_host

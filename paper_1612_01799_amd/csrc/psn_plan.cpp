@@ -1,0 +1,400 @@
+// C ABI: plan creation (geometry, near-zone radius, Gaussian-sum table and its
+// self-check), device state, and the entry points declared in psn.h.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "psn_internal.h"
+
+namespace {
+
+thread_local std::string g_last_error;
+
+// Record a failed HIP call (its name and HIP's message) and report it.
+bool hip_ok(hipError_t e, const char* what) {
+    if (e == hipSuccess) return true;
+    g_last_error = std::string(what) + ": " + hipGetErrorName(e) + " (" + hipGetErrorString(e) + ")";
+    (void)hipGetLastError();
+    return false;
+}
+
+constexpr double kPi = 3.14159265358979323846;
+
+bool five_smooth(long v) {
+    if (v <= 0) return false;
+    for (long f : {2L, 3L, 5L})
+        while (v % f == 0) v /= f;
+    return v == 1;
+}
+
+// Inverse of erfc by Newton's method on log(erfc(x)) (well conditioned for
+// the tiny arguments used here).
+double erfcinv(double y) {
+    double x = std::sqrt(-std::log(y));
+    for (int it = 0; it < 100; ++it) {
+        const double e = std::erfc(x);
+        const double g = std::log(e) - std::log(y);
+        const double dg = -2.0 / std::sqrt(kPi) * std::exp(-x * x) / e;
+        const double dx = g / dg;
+        x -= dx;
+        if (std::fabs(dx) < 1e-16 * x) break;
+    }
+    return x;
+}
+
+// max over log-spaced r in [delta, R] of |4 pi r U_GS(r) - 1|
+double gs_max_rel_error(const std::vector<double>& tau, const std::vector<double>& w, double delta, double R,
+                        int points) {
+    double worst = 0.0;
+    const double a = std::log(delta), b = std::log(R);
+    for (int i = 0; i < points; ++i) {
+        const double r = std::exp(a + (b - a) * i / (points - 1));
+        double s = 0.0;
+        for (size_t j = 0; j < tau.size(); ++j) s += w[j] * std::exp(-(tau[j] * r) * (tau[j] * r));
+        worst = std::fmax(worst, std::fabs(4.0 * kPi * r * s - 1.0));
+    }
+    return worst;
+}
+
+// Gaussian sum by sinc quadrature of 1/r = (2/sqrt(pi)) int exp(-r^2 e^{2t} + t) dt
+// (paper section 2): tau_j = exp(j hs), w_j = hs tau_j / (2 pi^{3/2}).  The
+// tolerance eps is split in quarters over the step error (the integrand is
+// analytic for |Im t| < pi/4), the tail t > t_max (relative error
+// erfc(r e^{t_max}) at r = delta) and the tail t < t_min (relative error
+// (2/sqrt(pi)) r e^{t_min} at r = R).  The fit is then checked on [delta, R];
+// on failure the step shrinks by 5 %.
+bool fit_gaussian_sum(psn_plan* p) {
+    const double ep = p->tol / 4.0;
+    double hs = kPi * kPi / (2.0 * std::log(2.0 / ep));
+    const double t_max = std::log(erfcinv(ep) / p->delta);
+    const double t_min = std::log(ep * std::sqrt(kPi) / (2.0 * p->R));
+    for (int attempt = 0; attempt < 20; ++attempt) {
+        const long j0 = (long)std::floor(t_min / hs), j1 = (long)std::ceil(t_max / hs);
+        p->tau.clear();
+        p->w.clear();
+        for (long j = j0; j <= j1; ++j) {
+            const double tj = std::exp(double(j) * hs);
+            p->tau.push_back(tj);
+            p->w.push_back(hs * tj / (2.0 * std::pow(kPi, 1.5)));
+        }
+        p->hs = hs;
+        p->gs_err = gs_max_rel_error(p->tau, p->w, p->delta, p->R, 32768);
+        if (p->gs_err <= p->tol) return true;
+        hs *= 0.95;
+    }
+    return false;
+}
+
+// 16-point Gauss-Legendre nodes and weights on [-1, 1] (Newton on P_16).
+void gauss_legendre16(double* x, double* wt) {
+    const int m = 16;
+    for (int i = 0; i < m; ++i) {
+        double z = std::cos(kPi * (i + 0.75) / (m + 0.5)), dp = 0.0;
+        for (int it = 0; it < 100; ++it) {
+            double p0 = 1.0, p1 = 0.0;
+            for (int k = 1; k <= m; ++k) {
+                const double p2 = p1;
+                p1 = p0;
+                p0 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p2) / k;
+            }
+            dp = m * (z * p0 - p1) / (z * z - 1.0);
+            const double dz = p0 / dp;
+            z -= dz;
+            if (std::fabs(dz) < 1e-17) break;
+        }
+        x[i] = z;
+        wt[i] = 2.0 / ((1.0 - z * z) * dp * dp);
+    }
+}
+
+struct DevBuf {
+    void* p = nullptr;
+    ~DevBuf() {
+        if (p) (void)hipFree(p);
+    }
+};
+
+psn_status dev_alloc(void** ptr, size_t bytes, size_t* total) {
+    if (!hip_ok(hipMalloc(ptr, bytes), "hipMalloc")) {
+        *ptr = nullptr;
+        return PSN_ENOMEM;
+    }
+    *total += bytes;
+    return PSN_OK;
+}
+
+void free_device(psn_plan* p) {
+    for (void** q : {&p->K, &p->Kb, &p->tw, &p->W1, &p->W2, &p->W1lo, &p->W2lo}) {
+        if (*q) (void)hipFree(*q);
+        *q = nullptr;
+    }
+    p->device_bytes = 0;
+    p->built = false;
+}
+
+bool is_real_dtype(int d) { return d == PSN_F64 || d == PSN_F32 || d == PSN_SPLIT; }
+
+}  // namespace
+
+namespace psn_host {
+
+size_t elem_bytes(psn_dtype dt) { return dt == PSN_F64 ? 16 : 8; }
+size_t kernel_elem_bytes(psn_dtype dt) { return dt == PSN_F32 ? 4 : 8; }
+
+}  // namespace psn_host
+
+extern "C" {
+
+int psn_size_supported(int n) {
+    return (n >= 4 && n % 2 == 0 && five_smooth(2L * n) && psn_host::size_compiled(n)) ? 1 : 0;
+}
+
+psn_status psn_plan_create(int n, double L, double tol, psn_dtype dtype, psn_plan** out) {
+    if (!out) return PSN_EINVAL;
+    *out = nullptr;
+    if (!is_real_dtype(dtype) || !(L > 0) || !std::isfinite(L) || !(tol >= 1e-15 && tol <= 1e-4))
+        return PSN_EINVAL;
+    if (!psn_size_supported(n)) return PSN_ESIZE;
+    psn_plan* p = new (std::nothrow) psn_plan();
+    if (!p) return PSN_ENOMEM;
+    p->n = n;
+    p->L = L;
+    p->tol = tol;
+    p->dtype = dtype;
+    p->h = 2.0 * L / (n - 1);
+    p->T = n * p->h;
+    p->period = 2.0 * n * p->h;
+    // section 3: delta = min_q (b_q - a_q) / (50 n_q) in the standardised frame,
+    // at least 1e-3; the physical radius is lambda (= L) times that.
+    const double delta_std = std::fmax(1e-3, 2.0 * L / (50.0 * n));
+    p->delta = L * delta_std;
+    p->R = 2.0 * std::sqrt(3.0) * L;
+    if (!fit_gaussian_sum(p)) {
+        delete p;
+        return PSN_EFIT;
+    }
+    *out = p;
+    return PSN_OK;
+}
+
+psn_status psn_kernel_build(psn_plan* p, void* stream) {
+    if (!p) return PSN_EINVAL;
+    if (p->built) return PSN_OK;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    g_last_error.clear();
+    (void)hipGetLastError();  // drop errors left by unrelated earlier calls
+    if (!hip_ok(hipGetDevice(&p->device), "hipGetDevice")) return PSN_EDEVICE;
+    const size_t n = p->n, M = 2 * n;
+    const size_t kb = psn_host::kernel_elem_bytes(p->dtype);
+    size_t tot = 0;
+    psn_status st = PSN_OK;
+    const size_t cxb = p->dtype == PSN_F32 ? 8 : 16;
+    const size_t wb = p->dtype == PSN_SPLIT ? 8 : psn_host::elem_bytes(p->dtype);
+    if ((st = dev_alloc(&p->K, (n + 1) * (n + 1) * n * kb, &tot)) ||
+        (st = dev_alloc(&p->Kb, (n + 1) * (n + 1) * kb, &tot)) || (st = dev_alloc(&p->tw, M * cxb, &tot)) ||
+        (st = dev_alloc(&p->W1, n * n * n * wb, &tot)) || (st = dev_alloc(&p->W2, n * M * n * wb, &tot))) {
+        free_device(p);
+        return st;
+    }
+    if (p->dtype == PSN_SPLIT) {
+        if ((st = dev_alloc(&p->W1lo, n * n * n * 4, &tot)) || (st = dev_alloc(&p->W2lo, n * M * n * 4, &tot))) {
+            free_device(p);
+            return st;
+        }
+    }
+    p->device_bytes = tot;
+
+    // twiddles exp(-2 pi i m / M), evaluated in extended precision, rounded once
+    std::vector<double> twd(2 * M);
+    for (size_t m = 0; m < M; ++m) {
+        const long double a = 2.0L * 3.14159265358979323846264338327950288L * (long double)m / (long double)M;
+        twd[2 * m] = (double)cosl(a);
+        twd[2 * m + 1] = (double)-sinl(a);
+    }
+    std::vector<float> twf;
+    const void* twsrc = twd.data();
+    if (p->dtype == PSN_F32) {
+        twf.assign(twd.begin(), twd.end());
+        twsrc = twf.data();
+    }
+    double glx[16], glw[16];
+    gauss_legendre16(glx, glw);
+    const int terms = (int)p->tau.size();
+
+    DevBuf d_tau, d_w, d_gl, d_A, d_c;
+    if ((st = dev_alloc(&d_tau.p, terms * 8, &tot)) || (st = dev_alloc(&d_w.p, terms * 8, &tot)) ||
+        (st = dev_alloc(&d_gl.p, 32 * 8, &tot)) || (st = dev_alloc(&d_A.p, size_t(terms) * (n + 1) * 8, &tot)) ||
+        (st = dev_alloc(&d_c.p, 2 * 8, &tot))) {
+        free_device(p);
+        return st;
+    }
+    std::vector<double> gl(32);
+    std::memcpy(gl.data(), glx, sizeof glx);
+    std::memcpy(gl.data() + 16, glw, sizeof glw);
+    double cc[2] = {0, 0};
+    bool ok = hip_ok(hipMemcpyAsync(p->tw, twsrc, M * cxb, hipMemcpyHostToDevice, s), "copy twiddles") &&
+              hip_ok(hipMemcpyAsync(d_tau.p, p->tau.data(), terms * 8, hipMemcpyHostToDevice, s), "copy tau") &&
+              hip_ok(hipMemcpyAsync(d_w.p, p->w.data(), terms * 8, hipMemcpyHostToDevice, s), "copy w") &&
+              hip_ok(hipMemcpyAsync(d_gl.p, gl.data(), 32 * 8, hipMemcpyHostToDevice, s), "copy nodes");
+    ok = ok && hip_ok(psn_host::launch_kernel_build(p, static_cast<double*>(d_tau.p), static_cast<double*>(d_w.p),
+                                                    terms, static_cast<double*>(d_gl.p),
+                                                    static_cast<double*>(d_gl.p) + 16, static_cast<double*>(d_A.p),
+                                                    static_cast<double*>(d_c.p), s),
+                      "kernel-spectrum launch");
+    ok = ok && hip_ok(hipMemcpyAsync(cc, d_c.p, sizeof cc, hipMemcpyDeviceToHost, s), "copy C0/C2");
+    ok = ok && hip_ok(hipStreamSynchronize(s), "hipStreamSynchronize");
+    if (!ok) {
+        free_device(p);
+        return PSN_EDEVICE;
+    }
+    p->C0 = cc[0];
+    p->C2 = cc[1];
+    p->built = true;
+    return PSN_OK;
+}
+
+psn_status psn_solve(psn_plan* p, const void* rho, void* u, void* stream) {
+    if (!p || !rho || !u) return PSN_EINVAL;
+    if (!p->built) return PSN_ESTATE;
+    int dev = -1;
+    if (!hip_ok(hipGetDevice(&dev), "hipGetDevice")) return PSN_EDEVICE;
+    if (dev != p->device) return PSN_EINVAL;
+    (void)hipGetLastError();
+    if (!hip_ok(psn_host::launch_solve(p, rho, u, static_cast<hipStream_t>(stream)), "solve launch"))
+        return PSN_EDEVICE;
+    return PSN_OK;
+}
+
+psn_status psn_solve_timed(psn_plan* p, const void* rho, void* u, void* stream, double* pass_ms) {
+    if (!p || !rho || !u || !pass_ms) return PSN_EINVAL;
+    if (!p->built) return PSN_ESTATE;
+    int dev = -1;
+    if (!hip_ok(hipGetDevice(&dev), "hipGetDevice")) return PSN_EDEVICE;
+    if (dev != p->device) return PSN_EINVAL;
+    (void)hipGetLastError();
+    hipEvent_t ev[6] = {};
+    for (auto& e : ev)
+        if (!hip_ok(hipEventCreate(&e), "hipEventCreate")) {
+            for (auto& f : ev)
+                if (f) (void)hipEventDestroy(f);
+            return PSN_EDEVICE;
+        }
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    bool ok = hip_ok(psn_host::launch_solve(p, rho, u, s, ev), "solve launch") &&
+              hip_ok(hipStreamSynchronize(s), "hipStreamSynchronize");
+    for (int i = 0; ok && i < 5; ++i) {
+        float ms = 0.f;
+        ok = hip_ok(hipEventElapsedTime(&ms, ev[i], ev[i + 1]), "hipEventElapsedTime");
+        pass_ms[i] = ms;
+    }
+    for (auto& e : ev) (void)hipEventDestroy(e);
+    return ok ? PSN_OK : PSN_EDEVICE;
+}
+
+psn_status psn_solve_batched(int count, psn_plan* const* plans, const void* const* rho, void* const* u,
+                             void* stream) {
+    if (count < 0 || (count > 0 && (!plans || !rho || !u))) return PSN_EINVAL;
+    for (int i = 0; i < count; ++i) {
+        if (!plans[i] || !rho[i] || !u[i]) return PSN_EINVAL;
+        if (!plans[i]->built) return PSN_ESTATE;
+    }
+    for (int i = 0; i < count; ++i) {
+        const psn_status st = psn_solve(plans[i], rho[i], u[i], stream);
+        if (st != PSN_OK) return st;
+    }
+    return PSN_OK;
+}
+
+psn_status psn_plan_query(const psn_plan* p, psn_plan_info* info) {
+    if (!p || !info) return PSN_EINVAL;
+    std::memset(info, 0, sizeof *info);
+    info->n = p->n;
+    info->dtype = p->dtype;
+    info->L = p->L;
+    info->tol = p->tol;
+    info->h = p->h;
+    info->T = p->T;
+    info->period = p->period;
+    info->delta = p->delta;
+    info->R = p->R;
+    info->hs = p->hs;
+    info->terms = (int)p->tau.size();
+    info->eps_achieved = p->gs_err;
+    info->C0 = p->C0;
+    info->C2 = p->C2;
+    info->built = p->built ? 1 : 0;
+    info->device_bytes = p->device_bytes;
+    // five passes, each one read and one write of its arrays (io: rho and u,
+    // s: complex intermediates per real, k: kernel spectrum per real)
+    const double n3 = double(p->n) * p->n * p->n, np1 = p->n + 1.0;
+    const double bio = p->dtype == PSN_F32 ? 4 : 8;
+    const double bs = p->dtype == PSN_F32 ? 4 : (p->dtype == PSN_F64 ? 8 : 6);
+    const double bk = p->dtype == PSN_F32 ? 4 : 8;
+    info->algorithmic_bytes = 2 * bio * n3 + 24 * bs * n3 + bk * np1 * np1 * np1;
+    return PSN_OK;
+}
+
+psn_status psn_plan_gs_table(const psn_plan* p, double* tau, double* w, int cap, int* terms) {
+    if (!p || !terms || cap < 0 || (cap > 0 && (!tau || !w))) return PSN_EINVAL;
+    const int m = (int)p->tau.size();
+    *terms = m;
+    for (int i = 0; i < m && i < cap; ++i) {
+        tau[i] = p->tau[i];
+        w[i] = p->w[i];
+    }
+    return PSN_OK;
+}
+
+psn_status psn_kernel_download(const psn_plan* p, double* octant) {
+    if (!p || !octant) return PSN_EINVAL;
+    if (!p->built) return PSN_ESTATE;
+    const size_t n = p->n, np1 = n + 1;
+    const size_t kb = psn_host::kernel_elem_bytes(p->dtype);
+    std::vector<unsigned char> hk(np1 * np1 * n * kb), hb(np1 * np1 * kb);
+    if (!hip_ok(hipMemcpy(hk.data(), p->K, hk.size(), hipMemcpyDeviceToHost), "copy K") ||
+        !hip_ok(hipMemcpy(hb.data(), p->Kb, hb.size(), hipMemcpyDeviceToHost), "copy Kb"))
+        return PSN_EDEVICE;
+    auto get = [&](const std::vector<unsigned char>& v, size_t i) -> double {
+        if (kb == 4) return (double)reinterpret_cast<const float*>(v.data())[i];
+        return reinterpret_cast<const double*>(v.data())[i];
+    };
+    const double M = 2.0 * n, inv = M * M * M;
+    for (size_t a = 0; a < np1; ++a)
+        for (size_t b = 0; b < np1; ++b) {
+            const size_t row = (b * np1 + a) * n;  // stored [k1][k0][k2]
+            double* dst = octant + (a * np1 + b) * np1;
+            const double al = get(hk, row), be = get(hb, b * np1 + a);
+            dst[0] = (al + be) * inv;
+            dst[n] = (al - be) * inv;
+            for (size_t c = 1; c < n; ++c) dst[c] = get(hk, row + c) * inv;
+        }
+    return PSN_OK;
+}
+
+void psn_plan_destroy(psn_plan* p) {
+    if (!p) return;
+    free_device(p);
+    delete p;
+}
+
+const char* psn_last_error(void) { return g_last_error.c_str(); }
+
+const char* psn_strerror(psn_status st) {
+    switch (st) {
+        case PSN_OK: return "success";
+        case PSN_EINVAL: return "invalid argument";
+        case PSN_ESIZE: return "unsupported grid size (n must be even, 2n 5-smooth, and compiled in)";
+        case PSN_ENOMEM: return "device allocation failed";
+        case PSN_EDEVICE: return "HIP call or kernel launch failed";
+        case PSN_ESTATE: return "kernel spectrum not built";
+        case PSN_EFIT: return "Gaussian-sum fit missed the tolerance";
+    }
+    return "unknown status";
+}
+
+}  // extern "C"

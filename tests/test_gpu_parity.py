@@ -1,0 +1,179 @@
+"""GPU path (through the C ABI) against the FP64 CPU oracle, element by element.
+
+Tolerances (max-norm relative error against the oracle): FP64 1e-12,
+split precision 1e-10, FP32 1e-5.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle as O
+import paper_cases as PC
+import workloads as W
+from gpu_common import TOL, gpu_solve, max_rel, oracle_octant, oracle_symbol, torch_cuda
+
+pytestmark = pytest.mark.gpu
+psn = pytest.importorskip("paper_1612_01799_amd")
+
+SIZES = [8, 12, 16, 24, 32, 48, 64, 96, 128, 160]
+
+
+def _mix(n, L, seed):
+    return W.mixture_density(W.draw_mixture(seed, 5, -L / 3, L / 3, 0.25 * L / 2, 0.45 * L / 2, 0.5, 1.5,
+                                            W.Box.cube(L, n)))
+
+
+@pytest.mark.parametrize("n", [8, 16, 32, 48])
+@pytest.mark.parametrize("dtype", ["f64", "f32", "split"])
+def test_kernel_spectrum_matches_oracle(n, dtype):
+    torch_cuda()
+    L = 2.0 + 0.1 * n
+    plan = psn.Plan(n, L, 1e-12, dtype).build()
+    K = plan.kernel_octant()
+    Ko = oracle_octant(n, L)
+    tol = 1e-13 if dtype != "f32" else 2e-7
+    assert np.max(np.abs(K - Ko)) <= tol * abs(Ko[0, 0, 0])
+    info = plan.info()
+    ks = O.kernel_spectrum(W.Box.cube(L, n), 1e-12)
+    assert info["C0"] == pytest.approx(ks.C0, rel=1e-12, abs=1e-18)
+    assert info["C2"] == pytest.approx(ks.C2, rel=1e-12, abs=1e-24)
+
+
+@pytest.mark.parametrize("n", SIZES)
+@pytest.mark.parametrize("dtype", ["f64", "f32", "split"])
+def test_solve_matches_oracle(n, dtype):
+    torch = torch_cuda()
+    print(f"case n={n} dtype={dtype}", flush=True)
+    L = 3.0
+    rho = _mix(n, L, 100 + n)
+    ref = O.solve(rho, oracle_symbol(n, L))
+    u = gpu_solve(psn, torch, n, L, dtype, rho)
+    assert max_rel(u, ref) <= TOL[dtype]
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32", "split"])
+def test_random_density_all_frequencies(dtype):
+    """White-noise density excites every frequency, including the packed
+    DC/Nyquist column and the self-conjugate rows of the middle pass."""
+    torch = torch_cuda()
+    n, L = 24, 1.7
+    rho = np.random.default_rng(5).standard_normal((n, n, n))
+    ref = O.solve(rho, oracle_symbol(n, L))
+    u = gpu_solve(psn, torch, n, L, dtype, rho)
+    assert max_rel(u, ref) <= TOL[dtype] * 10
+
+
+def _gpu_entries():
+    g = PC.load()
+    return [e for e in g["digits"] + g["three_digits"] if e["a"] == [-2, -2, -2] and e["b"] == [2, 2, 2]]
+
+
+@pytest.mark.parametrize("entry", _gpu_entries(), ids=[PC.name(e) for e in _gpu_entries()])
+def test_paper_tables_on_gpu_fp64(entry):
+    """The printed E of the cube tables, reproduced by the FP64 GPU path."""
+    torch = torch_cuda()
+    box, rho, ustar = PC.case(entry)
+    u = gpu_solve(psn, torch, box.n[0], 2.0, "f64", rho, tol=entry.get("eps", 1e-12))
+    E = O.error_E(u, ustar)
+    digits = 4 if entry in PC.load()["digits"] else 3
+    assert abs(E - entry["E"]) <= 0.5 * 10 ** (math.floor(math.log10(entry["E"])) - (digits - 1)) * 1.0001
+
+
+def test_single_gaussian_closed_form_fp64():
+    torch = torch_cuda()
+    mix = W.config_single()
+    u = gpu_solve(psn, torch, 32, 6.0, "f64", W.mixture_density(mix))
+    assert O.error_E(u, O.analytic.mixture(mix)) <= 1e-10
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32", "split"])
+def test_n128_mixture(dtype):
+    torch = torch_cuda()
+    mix = W.config_n128()
+    rho = W.mixture_density(mix)
+    ref = O.solve(rho, oracle_symbol(128, 8.0))
+    u = gpu_solve(psn, torch, 128, 8.0, dtype, rho)
+    assert max_rel(u, ref) <= TOL[dtype]
+    if dtype == "f64":
+        assert O.error_E(u, O.analytic.mixture(mix)) <= 1e-10
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32", "split"])
+def test_n256_mixture(dtype):
+    torch = torch_cuda()
+    mix = W.config_n256()
+    rho = W.mixture_density(mix)
+    ref = _n256_ref()
+    u = gpu_solve(psn, torch, 256, 10.0, dtype, rho)
+    assert max_rel(u, ref) <= TOL[dtype]
+
+
+_cache = {}
+
+
+def _n256_ref():
+    if "n256" not in _cache:
+        mix = W.config_n256()
+        _cache["n256"] = O.solve(W.mixture_density(mix), oracle_symbol(256, 10.0))
+    return _cache["n256"]
+
+
+def test_zero_density_gives_zero():
+    torch = torch_cuda()
+    for dt in ["f64", "f32", "split"]:
+        u = gpu_solve(psn, torch, 16, 1.0, dt, np.zeros((16, 16, 16)))
+        assert np.all(u == 0)
+
+
+def test_in_place_and_plan_reuse_and_determinism():
+    torch = torch_cuda()
+    n, L = 32, 2.5
+    plan = psn.Plan(n, L, 1e-12, "f32").build()
+    sym = oracle_symbol(n, L)
+    for seed in (1, 2):
+        rho_np = _mix(n, L, seed)
+        rho = torch.from_numpy(rho_np).to("cuda", torch.float32)
+        a = plan.solve(rho)
+        b = plan.solve(rho)
+        torch.cuda.synchronize()
+        assert torch.equal(a, b)
+        c = rho.clone()
+        plan.solve(c, out=c)
+        torch.cuda.synchronize()
+        assert torch.equal(a, c)
+        assert max_rel(a.double().cpu().numpy(), O.solve(rho_np, sym)) <= TOL["f32"]
+
+
+def test_side_stream():
+    torch = torch_cuda()
+    n, L = 32, 2.5
+    plan = psn.Plan(n, L, 1e-12, "f64").build()
+    rho_np = _mix(n, L, 3)
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        rho = torch.from_numpy(rho_np).to("cuda")
+        u = plan.solve(rho, stream=s)
+    s.synchronize()
+    assert max_rel(u.cpu().numpy(), O.solve(rho_np, oracle_symbol(n, L))) <= TOL["f64"]
+
+
+def test_batched_mixed_sizes():
+    torch = torch_cuda()
+    mixes = W.config_batched(count=10)
+    plans, rhos, refs = [], [], []
+    cache = {}
+    for mix in mixes:
+        n = mix.box.n[0]
+        L = mix.box.b[0]
+        if n not in cache:
+            cache[n] = psn.Plan(n, L, 1e-12, "f32").build()
+        plans.append(cache[n])
+        rho = W.mixture_density(mix)
+        rhos.append(torch.from_numpy(rho).to("cuda", torch.float32))
+        refs.append(O.solve(rho, oracle_symbol(n, L)))
+    outs = psn.solve_batched(plans, rhos)
+    torch.cuda.synchronize()
+    for u, ref in zip(outs, refs):
+        assert max_rel(u.double().cpu().numpy(), ref) <= TOL["f32"]
+    assert psn.solve_batched([], []) == []
