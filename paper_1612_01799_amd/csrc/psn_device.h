@@ -182,14 +182,39 @@ constexpr RadixPlan make_plan(int N, int E) {
 }
 
 // Elements per thread for a length-N line: all of N's odd factors times up to
-// 16 (N a power of two) or 4 (N with a factor 3 or 5) of its powers of two.
-constexpr int elems_per_thread(int N) {
+// 16 (N a power of two; 8 for 8-byte reals) or 4 (N with a factor 3 or 5) of
+// its powers of two.
+constexpr int elems_per_thread(int N, int real_bytes) {
     int odd = N;
     while (odd % 2 == 0) odd /= 2;
     int p2 = N / odd;
-    int cap = odd == 1 ? 16 : 4;
+    int cap = odd == 1 ? (real_bytes == 8 ? 8 : 16) : 4;
     return odd * (p2 < cap ? p2 : cap);
 }
+
+// ----------------------------------------------------------------- twiddle sources
+// exp(-2 pi i m / 2N) for m in [0, 2N)
+template <class Real>
+struct TwGlobal {
+    const cx<Real>* __restrict__ p;
+    __device__ __forceinline__ cx<Real> operator()(int m) const { return p[m]; }
+};
+template <class Real>
+struct TwLds {
+    const cx<Real>* p;
+    __device__ __forceinline__ cx<Real> operator()(int m) const { return p[m]; }
+};
+
+// Adapts a one-value LDS view to the cx[1] interface of TeamFFT::stage.
+template <class Lds>
+struct Single {
+    Lds& l;
+    template <class C>
+    __device__ __forceinline__ void put(int pos, const C (&v)[1]) { l.put(pos, v[0]); }
+    template <class C>
+    __device__ __forceinline__ void get(int pos, C (&v)[1]) const { v[0] = l.get(pos); }
+    __device__ __forceinline__ void sync() { l.sync(); }
+};
 
 // ----------------------------------------------------------------- team FFT
 // A team of T threads computes one length-N transform (DIR = -1 forward,
@@ -225,44 +250,75 @@ struct TeamFFT {
         return t + T * (e / RL) + (e % RL) * (N / RL);
     }
 
-    template <int I, class Lds>
-    static __device__ __forceinline__ void stage(cx<Real> (&d)[E], int t, const cx<Real>* __restrict__ tw,
-                                                 Lds& lds) {
+    // NC independent lines per thread advance together: one barrier pair per
+    // exchange serves all of them.  `lds` stores the NC values of one position
+    // together (put/get of cx[NC]); `tw(m)` returns exp(-2 pi i m / 2N).
+    template <int I, int NC, class Lds, class Tw>
+    static __device__ __forceinline__ void stage(cx<Real> (&d)[NC][E], int t, const Tw& tw, Lds& lds) {
         if constexpr (I < S) {
             constexpr int R = radix(I);
             constexpr int Ns = span(I);
-            constexpr int twstep = 2 * N / (Ns * R);  // table has 2N entries: exp(-2 pi i m / 2N)
+            constexpr int twstep = 2 * N / (Ns * R);
             if constexpr (I > 0) {
 #pragma unroll
-                for (int e = 0; e < E; ++e) d[e] = lds.get(t + T * (e / R) + (e % R) * (N / R));
+                for (int e = 0; e < E; ++e) {
+                    cx<Real> v[NC];
+                    lds.get(t + T * (e / R) + (e % R) * (N / R), v);
+#pragma unroll
+                    for (int c = 0; c < NC; ++c) d[c][e] = v[c];
+                }
             }
 #pragma unroll
             for (int s = 0; s < E / R; ++s) {
-                cx<Real>* v = d + s * R;
+                cx<Real> w[R];
                 if constexpr (Ns > 1) {
                     const int k = (t + T * s) % Ns;
 #pragma unroll
-                    for (int r = 1; r < R; ++r) v[r] = twmul<DIR>(v[r], tw[r * k * twstep]);
+                    for (int r = 1; r < R; ++r) w[r] = tw(r * k * twstep);
                 }
-                DFT<R, DIR, Real>::run(v);
+#pragma unroll
+                for (int c = 0; c < NC; ++c) {
+                    cx<Real>* v = d[c] + s * R;
+                    if constexpr (Ns > 1) {
+#pragma unroll
+                        for (int r = 1; r < R; ++r) v[r] = twmul<DIR>(v[r], w[r]);
+                    }
+                    DFT<R, DIR, Real>::run(v);
+                }
             }
             if constexpr (I + 1 < S) {
                 lds.sync();
 #pragma unroll
                 for (int e = 0; e < E; ++e) {
                     const int b = t + T * (e / R);
-                    lds.put((b / Ns) * Ns * R + (b % Ns) + (e % R) * Ns, d[e]);
+                    cx<Real> v[NC];
+#pragma unroll
+                    for (int c = 0; c < NC; ++c) v[c] = d[c][e];
+                    lds.put((b / Ns) * Ns * R + (b % Ns) + (e % R) * Ns, v);
                 }
                 lds.sync();
             }
-            stage<I + 1>(d, t, tw, lds);
+            stage<I + 1, NC>(d, t, tw, lds);
         }
     }
 
+    template <int NC, class Lds, class Tw>
+    static __device__ __forceinline__ void run(cx<Real> (&d)[NC][E], int t, const Tw& tw, Lds& lds) {
+        stage<0, NC>(d, t, tw, lds);
+    }
+
+    // single line per thread, twiddles from a global table
     template <class Lds>
     static __device__ __forceinline__ void run(cx<Real> (&d)[E], int t, const cx<Real>* __restrict__ tw,
                                                Lds& lds) {
-        stage<0>(d, t, tw, lds);
+        cx<Real> dd[1][E];
+#pragma unroll
+        for (int e = 0; e < E; ++e) dd[0][e] = d[e];
+        Single<Lds> l1{lds};
+        TwGlobal<Real> g{tw};
+        stage<0, 1>(dd, t, g, l1);
+#pragma unroll
+        for (int e = 0; e < E; ++e) d[e] = dd[0][e];
     }
 };
 
@@ -275,6 +331,26 @@ struct LdsCols {
     int col;
     __device__ __forceinline__ void put(int pos, cx<Real> v) { buf[pos * stride + col] = v; }
     __device__ __forceinline__ cx<Real> get(int pos) const { return buf[pos * stride + col]; }
+    __device__ __forceinline__ void sync() { __syncthreads(); }
+};
+
+// Strided passes, two chains per line stored side by side: element-major,
+// column next, chain fastest, so one 16-byte (FP32) access moves both chains.
+template <class Real>
+struct LdsCols2 {
+    cx<Real>* buf;
+    int stride;  // columns per element row
+    int col;
+    __device__ __forceinline__ void put(int pos, const cx<Real> (&v)[2]) {
+        cx<Real>* q = buf + 2 * (pos * stride + col);
+        q[0] = v[0];
+        q[1] = v[1];
+    }
+    __device__ __forceinline__ void get(int pos, cx<Real> (&v)[2]) const {
+        const cx<Real>* q = buf + 2 * (pos * stride + col);
+        v[0] = q[0];
+        v[1] = q[1];
+    }
     __device__ __forceinline__ void sync() { __syncthreads(); }
 };
 

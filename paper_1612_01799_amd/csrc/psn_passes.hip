@@ -4,7 +4,10 @@
 // Layout (C order, last index contiguous), M = 2n:
 //   rho, u : [i0][i1][i2]            n^3 reals
 //   W1     : [i0][i1][k2]            n^3 complex, k2 = 0..n-1
-//   W2     : [i0][k1][k2]            n * M * n complex
+//   W2     : [k1/KB][i0][k1%KB][k2]  n * M * n complex, blocked over k1 so that
+//            both the axis-1 passes (fixed i0, all k1) and the axis-0 pass
+//            (fixed k1, all i0) touch about sqrt(M) distinct 2 MB pages
+//            per line instead of M or n
 //   K      : [k1~][k0~][k2]          (n+1)^2 * n reals, folded k~ = min(k, M-k)
 //   Kb     : [k1~][k0~]              (n+1)^2 reals
 // The real-to-complex transform along axis 2 gives n+1 frequencies; the two
@@ -29,11 +32,18 @@
 
 namespace psn {
 
-constexpr int kMaxLds = 65536;
+constexpr int kMaxLds = 65536;       // per workgroup for the one-chain passes
+constexpr int kMaxLdsP3 = 163840;    // gfx950: 160 KB of LDS per workgroup
 
 constexpr int pick_cols(int N, int bmax, int sets, int cxbytes, int T) {
     for (int b = bmax; b >= 1; --b)
         if (N % b == 0 && sets * b * N * cxbytes <= kMaxLds && sets * b * T <= 1024) return b;
+    return 1;
+}
+
+constexpr int pick_cols_p3(int N, int bmax, int cxbytes, int T) {
+    for (int b = bmax; b >= 1; --b)
+        if (N % b == 0 && (2 * b * N + 2 * N) * cxbytes <= kMaxLdsP3 && b * T <= 1024) return b;
     return 1;
 }
 
@@ -46,17 +56,37 @@ constexpr int pick_lines(int N, int T, int cxbytes) {
     return l;
 }
 
+// k1 block of the W2 layout: the largest power of two <= sqrt(2N) dividing 2N
+constexpr int k1_block(int N) {
+    int kb = 1;
+    while ((2 * kb) * (2 * kb) <= 2 * N && (2 * N) % (2 * kb) == 0) kb *= 2;
+    return kb;
+}
+
+template <int N>
+struct W2Index {
+    static constexpr int KB = k1_block(N);
+    // element (i0, k1, k2)
+    static __device__ __forceinline__ size_t at(int i0, int k1, int k2) {
+        return (size_t(k1 / KB) * N + i0) * (size_t(KB) * N) + size_t(k1 % KB) * N + k2;
+    }
+    // stride between consecutive i0 at fixed (k1, k2)
+    static constexpr size_t s0 = size_t(KB) * N;
+};
+
 template <int N, int DT>
 struct Cfg {
     using P = Prec<DT>;
     using Real = typename P::Real;
     using Io = typename P::Io;
     using Kt = typename P::Kt;
-    static constexpr int E = elems_per_thread(N);
+    static constexpr int E = elems_per_thread(N, sizeof(Real));
     static constexpr int T = N / E;
     static constexpr int CX = sizeof(cx<Real>);
-    static constexpr int BS = pick_cols(N, DT == DT_F32 ? 16 : 8, 1, CX, T);   // P2, P4 columns
-    static constexpr int BP3 = pick_cols(N, DT == DT_F32 ? 8 : 4, 2, CX, T);   // P3 columns per set
+    static constexpr int T24 = N / elems_per_thread(N, 8);                     // P2, P4 team (two chains)
+    static constexpr int BS = pick_cols_p3(N, 8, CX, T24);                     // P2, P4 columns
+    static constexpr int T3 = N / elems_per_thread(N, 8);                      // P3 team (two chains)
+    static constexpr int BP3 = pick_cols_p3(N, DT == DT_F32 ? 8 : 4, CX, T3);  // P3 columns
     static constexpr int LC = pick_lines(N, T, CX);                            // P1, P5 lines
     static constexpr int NP = rows_padded(N);
 };
@@ -107,96 +137,183 @@ p1_r2c(const typename Cfg<N, DT>::Io* __restrict__ rho, Work<DT> w1,
     }
 }
 
+// Workgroup ids are dealt to the XCDs round robin; give each XCD a contiguous
+// run of units so neighbouring tiles (which may share 128-byte lines) meet in
+// the same L2.
+__device__ __forceinline__ int xcd_unit() {
+    const int g = blockIdx.x;
+    return (g % 8) * (gridDim.x / 8) + g / 8;
+}
+
 // ------------------------------------------------------------------ P2
-template <int N, int DT>
-__global__ void __launch_bounds__((Cfg<N, DT>::BS * Cfg<N, DT>::T))
-p2_fwd(Work<DT> w1, Work<DT> w2, const cx<typename Cfg<N, DT>::Real>* __restrict__ tw) {
+// Unit = (i0, tile of B columns k2).  Both outputs of a line (DFT_n of x and
+// of x w^j) are computed in lockstep from the same loads.
+template <int N, int DT, int B, int TT>
+__global__ void __launch_bounds__((B * TT))
+p2_fwd(Work<DT> w1, Work<DT> w2, const cx<typename Cfg<N, DT>::Real>* __restrict__ tw, int units) {
     using C = Cfg<N, DT>;
     using Real = typename C::Real;
-    using F = TeamFFT<N, C::T, Real, -1, false>;
+    using F = TeamFFT<N, TT, Real, -1, false>;
+    using WI = W2Index<N>;
+    constexpr int E = F::E;
+    constexpr int tiles = N / B;
     extern __shared__ __align__(16) unsigned char smem[];
     cx<Real>* sb = reinterpret_cast<cx<Real>*>(smem);
-    const int c = threadIdx.x % C::BS, t = threadIdx.x / C::BS;
-    const int k2 = blockIdx.x * C::BS + c;
-    const size_t i0 = blockIdx.y;
-    const size_t inb = i0 * N * N + k2;
-    const size_t outb = i0 * (2 * N) * N + k2;
+    cx<Real>* stw = sb + 2 * B * N;
+    const int u = xcd_unit();
+    if (u >= units) return;
+    const int i0 = u / tiles, tile = u % tiles;
+    const int c = threadIdx.x % B, t = threadIdx.x / B;
+    const int k2 = tile * B + c;
+    const size_t inb = size_t(i0) * N * N + k2;
 
-    cx<Real> x[F::E];
+    cx<Real> d[2][E], w[E];
 #pragma unroll
-    for (int e = 0; e < F::E; ++e) x[e] = w1.ld(inb + size_t(F::in_pos(t, e)) * N);
-    LdsCols<Real> lds{sb, C::BS, c};
+    for (int e = 0; e < E; ++e) {
+        const int pos = F::in_pos(t, e);
+        d[0][e] = w1.ld(inb + size_t(pos) * N);
+        w[e] = tw[pos];
+    }
+    for (int i = threadIdx.x; i < 2 * N; i += B * TT) stw[i] = tw[i];
 #pragma unroll
-    for (int p = 0; p < 2; ++p) {
-        cx<Real> d[F::E];
+    for (int e = 0; e < E; ++e) d[1][e] = d[0][e] * w[e];
+    LdsCols2<Real> lds{sb, B, c};
+    TwLds<Real> tl{stw};
+    F::template run<2>(d, t, tl, lds);
 #pragma unroll
-        for (int e = 0; e < F::E; ++e) d[e] = p ? x[e] * tw[F::in_pos(t, e)] : x[e];
-        F::run(d, t, tw, lds);
-#pragma unroll
-        for (int e = 0; e < F::E; ++e) w2.st(outb + size_t(2 * F::out_pos(t, e) + p) * N, d[e]);
+    for (int e = 0; e < E; ++e) {
+        const int m = F::out_pos(t, e);
+        w2.st(WI::at(i0, 2 * m, k2), d[0][e]);
+        w2.st(WI::at(i0, 2 * m + 1, k2), d[1][e]);
     }
 }
 
 // ------------------------------------------------------------------ P3
-template <int N, int DT>
-__global__ void __launch_bounds__((2 * Cfg<N, DT>::BP3 * Cfg<N, DT>::T))
+// One workgroup = one row k1 of W2 and B adjacent columns k2.  The two parity
+// chains (even and odd k0) of each line advance in lockstep, stored side by
+// side in LDS, so one pair of barriers and one 16-byte access per element
+// serve both.  Workgroup ids are dealt to the XCDs round robin; each XCD gets
+// a contiguous run of units (unit = one row of one tile, rows k1 and M-k1 of a
+// tile back to back), so tiles sharing 128-byte lines and rows sharing a
+// kernel row meet in the same L2.  All global loads (data, the pre/post
+// twiddles of the odd chain and the kernel values) are issued before any
+// arithmetic; the stage twiddles come from a copy of the table in LDS.
+// Column 0 (the packed k2 = 0 / k2 = n pair) is left to p3_col0.
+template <int N, int DT, int B, int TT>
+__global__ void __launch_bounds__((B * TT))
 p3_conv(Work<DT> w2, const typename Cfg<N, DT>::Kt* __restrict__ K,
+        const cx<typename Cfg<N, DT>::Real>* __restrict__ tw, int items) {
+    using C = Cfg<N, DT>;
+    using Real = typename C::Real;
+    using Ff = TeamFFT<N, TT, Real, -1, false>;
+    using Fi = TeamFFT<N, TT, Real, +1, true>;
+    constexpr int E = Ff::E;
+    constexpr int tiles = N / B;
+    constexpr size_t s0 = W2Index<N>::s0;  // stride of i0 in W2
+    extern __shared__ __align__(16) unsigned char smem[];
+    cx<Real>* sb = reinterpret_cast<cx<Real>*>(smem);
+    cx<Real>* stw = sb + 2 * B * N;
+
+    const int g = blockIdx.x;
+    const int u = (g % 8) * (gridDim.x / 8) + g / 8;
+    const int item = u >> 1, set = u & 1;
+    if (item >= items) return;  // whole workgroup
+    const int q = item / tiles, tile = item % tiles;
+    const int k1 = set == 0 ? q : (q == 0 ? N : 2 * N - q);
+    const int kt1 = k1 <= N ? k1 : 2 * N - k1;
+    const int c = threadIdx.x % B, t = threadIdx.x / B;
+    const int k2 = tile * B + c;
+    const size_t base = W2Index<N>::at(0, k1, k2);
+    const typename C::Kt* Krow = K + size_t(kt1) * (N + 1) * N + k2;
+
+    cx<Real> x[E], w[E];
+    Real ke[E], ko[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const int pos = Ff::in_pos(t, e);
+        x[e] = w2.ld(base + size_t(pos) * s0);
+        w[e] = tw[pos];
+    }
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const int m = Ff::out_pos(t, e);
+        const int a = 2 * m, b = 2 * m + 1;
+        ke[e] = Real(Krow[size_t(a <= N ? a : 2 * N - a) * N]);
+        ko[e] = Real(Krow[size_t(b <= N ? b : 2 * N - b) * N]);
+    }
+    for (int i = threadIdx.x; i < 2 * N; i += B * TT) stw[i] = tw[i];  // visible after the first exchange
+
+    cx<Real> d[2][E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        d[0][e] = x[e];
+        d[1][e] = x[e] * w[e];
+    }
+    LdsCols2<Real> lds{sb, B, c};
+    TwLds<Real> tl{stw};
+    Ff::template run<2>(d, t, tl, lds);
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        d[0][e] = scale(d[0][e], ke[e]);
+        d[1][e] = scale(d[1][e], ko[e]);
+    }
+    Fi::template run<2>(d, t, tl, lds);
+    if (k2 != 0) {
+#pragma unroll
+        for (int e = 0; e < E; ++e)
+            w2.st(base + size_t(Fi::out_pos(t, e)) * s0, d[0][e] + mul_conj(d[1][e], w[e]));
+    }
+}
+
+// Column 0 of W2 carries Z = A + iB with A, B the spectra of the real k2 = 0
+// and k2 = n planes.  With the partner row -k the product is
+// Z' = a Z(k) + b conj(Z(-k)), a = (K0+Kn)/2 (stored in K's column 0) and
+// b = (K0-Kn)/2 (stored in Kb).  One workgroup holds rows q and M-q (row 0
+// pairs with itself, as does row n).
+template <int N, int DT>
+__global__ void __launch_bounds__((2 * Cfg<N, DT>::T))
+p3_col0(Work<DT> w2, const typename Cfg<N, DT>::Kt* __restrict__ K,
         const typename Cfg<N, DT>::Kt* __restrict__ Kb, const cx<typename Cfg<N, DT>::Real>* __restrict__ tw) {
     using C = Cfg<N, DT>;
     using Real = typename C::Real;
     using Ff = TeamFFT<N, C::T, Real, -1, false>;
     using Fi = TeamFFT<N, C::T, Real, +1, true>;
-    static_assert(Ff::E == Fi::E, "");
-    constexpr int B = C::BP3;
-    constexpr size_t s0 = size_t(2 * N) * N;  // stride of i0 in W2
+    constexpr size_t s0 = W2Index<N>::s0;
     extern __shared__ __align__(16) unsigned char smem[];
     cx<Real>* sb = reinterpret_cast<cx<Real>*>(smem);
 
-    const int c = threadIdx.x % B;
-    const int set = (threadIdx.x / B) & 1;
-    const int t = threadIdx.x / (2 * B);
-    const int q = blockIdx.y;
-    // sets pair k1 with -k1 (mod M); pair 0 holds the two self-conjugate rows 0 and n
+    const int set = threadIdx.x & 1;
+    const int t = threadIdx.x >> 1;
+    const int q = blockIdx.x;
     const int k1 = set == 0 ? q : (q == 0 ? N : 2 * N - q);
     const int kt1 = (q == 0) ? (set ? N : 0) : q;
     const int partner = (q == 0) ? set : 1 - set;
-    const int k2 = blockIdx.x * B + c;
-    const bool colzero = blockIdx.x == 0;  // workgroup-uniform
-    const size_t base = size_t(k1) * N + k2;
-    const typename C::Kt* Krow = K + size_t(kt1) * (N + 1) * N + k2;
+    const size_t base = W2Index<N>::at(0, k1, 0);
+    const typename C::Kt* Krow = K + size_t(kt1) * (N + 1) * N;
     const typename C::Kt* Kbr = Kb + size_t(kt1) * (N + 1);
 
     cx<Real> x[Ff::E], acc[Ff::E];
 #pragma unroll
     for (int e = 0; e < Ff::E; ++e) x[e] = w2.ld(base + size_t(Ff::in_pos(t, e)) * s0);
-    LdsCols<Real> lds{sb + set * B, 2 * B, c};
+    LdsCols<Real> lds{sb + set, 2, 0};
 #pragma unroll
     for (int p = 0; p < 2; ++p) {
         cx<Real> d[Ff::E];
 #pragma unroll
         for (int e = 0; e < Ff::E; ++e) d[e] = p ? x[e] * tw[Ff::in_pos(t, e)] : x[e];
         Ff::run(d, t, tw, lds);
-        if (colzero) {
-            __syncthreads();
-            if (c == 0) {
+        __syncthreads();
 #pragma unroll
-                for (int e = 0; e < Ff::E; ++e) sb[set * N + Ff::out_pos(t, e)] = d[e];
-            }
-            __syncthreads();
-        }
+        for (int e = 0; e < Ff::E; ++e) sb[set * N + Ff::out_pos(t, e)] = d[e];
+        __syncthreads();
 #pragma unroll
         for (int e = 0; e < Ff::E; ++e) {
             const int m = Ff::out_pos(t, e);
             const int k0 = 2 * m + p;
             const int kt0 = k0 <= N ? k0 : 2 * N - k0;
-            const Real kv = Real(Krow[size_t(kt0) * N]);
-            if (colzero && c == 0) {
-                const int mp = p == 0 ? (m == 0 ? 0 : N - m) : N - 1 - m;
-                const cx<Real> zp = conj(sb[partner * N + mp]);
-                d[e] = scale(d[e], kv) + scale(zp, Real(Kbr[kt0]));
-            } else {
-                d[e] = scale(d[e], kv);
-            }
+            const int mp = p == 0 ? (m == 0 ? 0 : N - m) : N - 1 - m;
+            const cx<Real> zp = conj(sb[partner * N + mp]);
+            d[e] = scale(d[e], Real(Krow[size_t(kt0) * N])) + scale(zp, Real(Kbr[kt0]));
         }
         Fi::run(d, t, tw, lds);
 #pragma unroll
@@ -210,36 +327,42 @@ p3_conv(Work<DT> w2, const typename Cfg<N, DT>::Kt* __restrict__ K,
 }
 
 // ------------------------------------------------------------------ P4
-template <int N, int DT>
-__global__ void __launch_bounds__((Cfg<N, DT>::BS * Cfg<N, DT>::T))
-p4_inv(Work<DT> w2, Work<DT> w1, const cx<typename Cfg<N, DT>::Real>* __restrict__ tw) {
+// Unit = (i0, tile of B columns k2).  The even and odd rows of a line are
+// inverted in lockstep and combined as y = y_even + w^-j y_odd.
+template <int N, int DT, int B, int TT>
+__global__ void __launch_bounds__((B * TT))
+p4_inv(Work<DT> w2, Work<DT> w1, const cx<typename Cfg<N, DT>::Real>* __restrict__ tw, int units) {
     using C = Cfg<N, DT>;
     using Real = typename C::Real;
-    using F = TeamFFT<N, C::T, Real, +1, false>;
+    using F = TeamFFT<N, TT, Real, +1, false>;
+    using WI = W2Index<N>;
+    constexpr int E = F::E;
+    constexpr int tiles = N / B;
     extern __shared__ __align__(16) unsigned char smem[];
     cx<Real>* sb = reinterpret_cast<cx<Real>*>(smem);
-    const int c = threadIdx.x % C::BS, t = threadIdx.x / C::BS;
-    const int k2 = blockIdx.x * C::BS + c;
-    const size_t i0 = blockIdx.y;
-    const size_t inb = i0 * (2 * N) * N + k2;
-    const size_t outb = i0 * N * N + k2;
+    cx<Real>* stw = sb + 2 * B * N;
+    const int u = xcd_unit();
+    if (u >= units) return;
+    const int i0 = u / tiles, tile = u % tiles;
+    const int c = threadIdx.x % B, t = threadIdx.x / B;
+    const int k2 = tile * B + c;
+    const size_t outb = size_t(i0) * N * N + k2;
 
-    cx<Real> acc[F::E];
-    LdsCols<Real> lds{sb, C::BS, c};
+    cx<Real> d[2][E], w[E];
 #pragma unroll
-    for (int p = 0; p < 2; ++p) {
-        cx<Real> d[F::E];
-#pragma unroll
-        for (int e = 0; e < F::E; ++e) d[e] = w2.ld(inb + size_t(2 * F::in_pos(t, e) + p) * N);
-        F::run(d, t, tw, lds);
-#pragma unroll
-        for (int e = 0; e < F::E; ++e) {
-            if (p == 0) acc[e] = d[e];
-            else acc[e] = acc[e] + mul_conj(d[e], tw[F::out_pos(t, e)]);
-        }
+    for (int e = 0; e < E; ++e) {
+        const int pos = F::in_pos(t, e);
+        d[0][e] = w2.ld(WI::at(i0, 2 * pos, k2));
+        d[1][e] = w2.ld(WI::at(i0, 2 * pos + 1, k2));
+        w[e] = tw[F::out_pos(t, e)];
     }
+    for (int i = threadIdx.x; i < 2 * N; i += B * TT) stw[i] = tw[i];
+    LdsCols2<Real> lds{sb, B, c};
+    TwLds<Real> tl{stw};
+    F::template run<2>(d, t, tl, lds);
 #pragma unroll
-    for (int e = 0; e < F::E; ++e) w1.st(outb + size_t(F::out_pos(t, e)) * N, acc[e]);
+    for (int e = 0; e < E; ++e)
+        w1.st(outb + size_t(F::out_pos(t, e)) * N, d[0][e] + mul_conj(d[1][e], w[e]));
 }
 
 // ------------------------------------------------------------------ P5
@@ -284,6 +407,12 @@ p5_c2r(Work<DT> w1, typename Cfg<N, DT>::Io* __restrict__ u, const cx<typename C
 }
 
 // ------------------------------------------------------------------ launcher
+// Kernels needing more than 64 KB of dynamic LDS must say so once.
+inline bool allow_lds(const void* fn, size_t bytes) {
+    if (bytes <= 65536) return true;
+    return hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, int(bytes)) == hipSuccess;
+}
+
 template <int N, int DT>
 hipError_t solve_n(const psn_plan* p, const void* rho_, void* u_, hipStream_t s, hipEvent_t* ev) {
     using C = Cfg<N, DT>;
@@ -304,8 +433,18 @@ hipError_t solve_n(const psn_plan* p, const void* rho_, void* u_, hipStream_t s,
         w2 = {static_cast<cx<Real>*>(p->W2)};
     }
     const size_t lds_rows = size_t(C::LC) * C::NP * C::CX;
-    const size_t lds_cols = size_t(C::BS) * N * C::CX;
-    const size_t lds_p3 = size_t(2) * C::BP3 * N * C::CX;
+    const size_t lds_cols = (size_t(2) * C::BS * N + 2 * N) * C::CX;
+    const int units24 = N * (N / C::BS);
+    const int grid24 = 8 * ((units24 + 7) / 8);
+    static const bool lds24_ok = allow_lds(reinterpret_cast<const void*>(&p2_fwd<N, DT, C::BS, C::T24>), lds_cols) &&
+                                 allow_lds(reinterpret_cast<const void*>(&p4_inv<N, DT, C::BS, C::T24>), lds_cols);
+    if (!lds24_ok) return hipErrorInvalidConfiguration;
+    const size_t lds_p3 = (size_t(2) * C::BP3 * N + 2 * N) * C::CX;
+    const size_t lds_c0 = size_t(2) * N * C::CX;
+    const int items = N * (N / C::BP3);
+    const int grid_p3 = 8 * ((2 * items + 7) / 8);
+    static const bool lds_ok = allow_lds(reinterpret_cast<const void*>(&p3_conv<N, DT, C::BP3, C::T3>), lds_p3);
+    if (!lds_ok) return hipErrorInvalidConfiguration;
 
     auto mark = [&](int i) {
         if (ev) (void)hipEventRecord(ev[i], s);
@@ -313,11 +452,15 @@ hipError_t solve_n(const psn_plan* p, const void* rho_, void* u_, hipStream_t s,
     mark(0);
     hipLaunchKernelGGL((p1_r2c<N, DT>), dim3(N * N / C::LC), dim3(C::LC * C::T), lds_rows, s, rho, w1, tw);
     mark(1);
-    hipLaunchKernelGGL((p2_fwd<N, DT>), dim3(N / C::BS, N), dim3(C::BS * C::T), lds_cols, s, w1, w2, tw);
+    hipLaunchKernelGGL((p2_fwd<N, DT, C::BS, C::T24>), dim3(grid24), dim3(C::BS * C::T24), lds_cols, s, w1, w2, tw,
+                       units24);
     mark(2);
-    hipLaunchKernelGGL((p3_conv<N, DT>), dim3(N / C::BP3, N), dim3(2 * C::BP3 * C::T), lds_p3, s, w2, K, Kb, tw);
+    hipLaunchKernelGGL((p3_conv<N, DT, C::BP3, C::T3>), dim3(grid_p3), dim3(C::BP3 * C::T3), lds_p3, s, w2, K, tw,
+                       items);
+    hipLaunchKernelGGL((p3_col0<N, DT>), dim3(N), dim3(2 * C::T), lds_c0, s, w2, K, Kb, tw);
     mark(3);
-    hipLaunchKernelGGL((p4_inv<N, DT>), dim3(N / C::BS, N), dim3(C::BS * C::T), lds_cols, s, w2, w1, tw);
+    hipLaunchKernelGGL((p4_inv<N, DT, C::BS, C::T24>), dim3(grid24), dim3(C::BS * C::T24), lds_cols, s, w2, w1, tw,
+                       units24);
     mark(4);
     hipLaunchKernelGGL((p5_c2r<N, DT>), dim3(N * N / C::LC), dim3(C::LC * C::T), lds_rows, s, w1, u, tw);
     mark(5);
