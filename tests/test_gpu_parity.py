@@ -177,3 +177,21 @@ def test_batched_mixed_sizes():
     for u, ref in zip(outs, refs):
         assert max_rel(u.double().cpu().numpy(), ref) <= TOL["f32"]
     assert psn.solve_batched([], []) == []
+
+
+_cache512 = {}
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f64", "split"])
+def test_n512_mixture_full_size(dtype):
+    """n = 512 on [-12,12]^3 (the benchmark workload, 128 Gaussians), full
+    oracle solve (padded 1024^3 in FP64 on the host), same launch
+    configuration as the benchmark."""
+    torch = torch_cuda()
+    mix = W.config_n512()
+    if "ref" not in _cache512:
+        rho = W.mixture_density(mix)
+        _cache512["rho"] = rho
+        _cache512["ref"] = O.solve(rho, O.half_spectrum(O.kernel_spectrum(mix.box, 1e-12)))
+    u = gpu_solve(psn, torch, 512, 12.0, dtype, _cache512["rho"])
+    assert max_rel(u, _cache512["ref"]) <= TOL[dtype]
