@@ -49,6 +49,25 @@ def pass_bytes(n, dtype):
             (2 * bs + bio) * n3]
 
 
+def measured_traffic(n, kernel):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 PMC summary,
+    or None if there is none for this size or the kernel sources changed since."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"solve_n{n}_f32_hbm_traffic.txt")
+    if kernel != "P3_fwd_mulK_inv_axis0" or not os.path.exists(path):
+        return None
+    src = b"".join(open(os.path.join(ROOT, "paper_1612_01799_amd", "csrc", f), "rb").read()
+                   for f in ("psn_device.h", "psn_passes.hip"))
+    digest = hashlib.sha256(src).hexdigest()[:16]
+    total, recorded = None, None
+    for line in open(path):
+        if line.startswith("# kernel sources sha256[:16]"):
+            recorded = line.split(":")[-1].strip()
+        if line.startswith(f"psn::p3_conv<{n}, 1,"):
+            total = float(line.split()[-3]) * 1e9
+    return total if (total is not None and recorded == digest) else None
+
+
 def time_path(psn, torch, n, L, dtype, rho64, steps, warmup):
     plan = psn.Plan(n, L, 1e-12, dtype).build()
     rho = rho64.to(plan.io_dtype()).contiguous()
@@ -174,7 +193,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": desc, "n": n, "padded": 2 * n, "path": "f32", "tol": 1e-12},
         "roofline": {"bound": "hbm", "kernel": PASS_NAMES[dom], "achieved": achieved / 1e9, "peak": HBM_PEAK / 1e9,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK, "traffic": None,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK, "traffic": measured_traffic(n, PASS_NAMES[dom]),
+                     "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE/WRITE_SIZE, copy-calibrated)",
                      "algorithmic_bytes_per_launch": pb[dom], "avg_ms": float(passes[dom])},
         "pass_ms": {PASS_NAMES[i]: float(passes[i]) for i in range(5)},
         "hbm_frac_whole_solve": info32["algorithmic_bytes"] / (ms32 * 1e-3) / HBM_PEAK,
