@@ -87,6 +87,62 @@ def time_path(psn, torch, n, L, dtype, rho64, steps, warmup):
     return plan, rho, out, ms
 
 
+def bench_batched(psn, torch, np, steps, warmup, with_oracle):
+    """64 densities of edges {48,...,160} (h = 0.1), FP32, one captured batch."""
+    import workloads as W
+    mixes = W.config_batched()
+    plans, rhos, cache = [], [], {}
+    for mix in mixes:
+        n, L = mix.box.n[0], mix.box.b[0]
+        if n not in cache:
+            cache[n] = psn.Plan(n, L, 1e-12, "f32").build()
+        plans.append(cache[n])
+        rhos.append(torch.from_numpy(W.mixture_density(mix)).to("cuda", torch.float32))
+    outs = [torch.empty_like(r) for r in rhos]
+    for _ in range(max(1, warmup)):
+        psn.solve_batched(plans, rhos, outs)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    t0.record(stream)
+    for _ in range(steps):
+        psn.solve_batched(plans, rhos, outs, stream=stream)
+    t1.record(stream)
+    torch.cuda.synchronize()
+    ms = t0.elapsed_time(t1) / steps
+    # the same solves one by one on the plans' own workspaces
+    tmp = [torch.empty_like(r) for r in rhos]
+    for p, r, o in zip(plans, rhos, tmp):
+        p.solve(r, o)
+    torch.cuda.synchronize()
+    t0.record(stream)
+    for _ in range(steps):
+        for p, r, o in zip(plans, rhos, tmp):
+            p.solve(r, o, stream=stream)
+    t1.record(stream)
+    torch.cuda.synchronize()
+    ms_seq = t0.elapsed_time(t1) / steps
+    pts = sum(float(p.n) ** 3 for p in plans)
+    byts = sum(p.info()["algorithmic_bytes"] for p in plans)
+    out = {"workload": "64 seeded 4-Gaussian densities, edges uniform from {48,64,96,128,160}, h = 0.1 "
+                       "(seed 1004), FP32, one graph-captured batch",
+           "count": len(plans), "grid_points": pts, "ms_per_batch": ms, "value": pts / (ms * 1e-3),
+           "unit": "grid pts/s", "hbm_frac": byts / (ms * 1e-3) / HBM_PEAK, "algorithmic_bytes": byts,
+           "ms_one_by_one": ms_seq, "max_rel_err_vs_oracle": None}
+    if with_oracle:
+        import oracle as O
+        sym, worst = {}, 0.0
+        for mix, u in zip(mixes, outs):
+            n, L = mix.box.n[0], mix.box.b[0]
+            if n not in sym:
+                sym[n] = O.half_spectrum(O.kernel_spectrum(mix.box, 1e-12))
+            ref = O.solve(W.mixture_density(mix), sym[n], workers=min(16, os.cpu_count() or 1))
+            worst = max(worst, float(np.max(np.abs(u.double().cpu().numpy() - ref)) / np.max(np.abs(ref))))
+        out["max_rel_err_vs_oracle"] = worst
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -95,6 +151,7 @@ def main():
     ap.add_argument("--n", type=int, default=512)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-compare", action="store_true", help="skip the FP64 and split paths")
+    ap.add_argument("--no-batched", action="store_true", help="skip the mixed-size batched workload")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one 1 GiB device-to-device tensor copy (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -177,6 +234,13 @@ def main():
             errs[k] = float(np.max(np.abs(v - uref)) / scale)
         log("oracle errors: " + ", ".join(f"{k}={v:.2e}" for k, v in errs.items()))
 
+    batched = None
+    if not args.no_batched:
+        log("timing the batched mixed-size workload")
+        batched = bench_batched(psn, torch, np, max(3, args.steps // 2), args.warmup, not args.no_cpu)
+        log(f"batched: {batched['ms_per_batch']:.3f} ms/batch ({batched['ms_one_by_one']:.3f} ms one by one), "
+            f"err {batched['max_rel_err_vs_oracle']}")
+
     value = n ** 3 / (ms32 * 1e-3)
     line = {
         "metric": "grid pts/s per solve at 256^3/512^3 vs FP64 path, max rel err, % HBM peak",
@@ -204,6 +268,7 @@ def main():
         "split_path": extra.get("split"),
         "speedup_vs_f64": (extra["f64"]["ms_per_step"] / ms32) if "f64" in extra else None,
         "max_rel_err_vs_oracle": errs or None,
+        "batched": batched,
     }
     print(json.dumps(line), flush=True)
 

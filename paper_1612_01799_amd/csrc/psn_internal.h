@@ -37,12 +37,22 @@ struct psn_plan {
 
 namespace psn_host {
 
-// One solve: five passes enqueued on `stream`.  Returns hipSuccess or the
-// launch error.
-// With `ev` non-null, ev[0] is recorded before the first pass and ev[i] after
-// pass i (i = 1..5).
-hipError_t launch_solve(const psn_plan* p, const void* rho, void* u, hipStream_t stream,
-                        hipEvent_t* ev = nullptr);
+// One problem of a solve: its plan (kernel spectrum, twiddles), its input and
+// output, and the workspace it runs in (the plan's own, or a batch arena's).
+struct Slot {
+    const psn_plan* plan;
+    const void* rho;
+    void* u;
+    void* W1;
+    void* W2;
+    void* W1lo;
+    void* W2lo;
+};
+
+// Enqueue the passes for `count` slots that share n and precision (one launch
+// per pass per 32 slots).  With `ev` non-null, ev[0] is recorded before the
+// first pass and ev[i] after pass i (i = 1..5).
+hipError_t launch_group(const Slot* slots, int count, hipStream_t stream, hipEvent_t* ev = nullptr);
 
 // Kernel spectrum build on the device (FP64), written into p->K / p->Kb in
 // the plan's storage type, plus C0/C2 into the two doubles at d_c.

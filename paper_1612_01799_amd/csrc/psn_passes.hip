@@ -91,19 +91,56 @@ struct Cfg {
     static constexpr int NP = rows_padded(N);
 };
 
+// One launch serves up to kMaxBatch problems of the same size.  The table
+// travels by value in the kernel arguments (no device copy, capturable in a
+// graph); workgroup units are numbered problem-major.
+constexpr int kMaxBatch = 32;
+
+template <int DT>
+struct Prob {
+    const typename Prec<DT>::Io* rho;
+    typename Prec<DT>::Io* u;
+    Work<DT> w1, w2;
+    const typename Prec<DT>::Kt* K;
+    const typename Prec<DT>::Kt* Kb;
+    const cx<typename Prec<DT>::Real>* tw;
+};
+
+template <int DT>
+struct Batch {
+    int count;
+    Prob<DT> p[kMaxBatch];
+};
+
+// Workgroup ids are dealt to the XCDs round robin; give each XCD a contiguous
+// run of units so neighbouring tiles (which may share 128-byte lines) meet in
+// the same L2.
+__device__ __forceinline__ int xcd_unit() {
+    const int g = blockIdx.x;
+    return (g % 8) * (gridDim.x / 8) + g / 8;
+}
+
+// Grid size for `units` units dealt by xcd_unit().
+inline int xcd_grid(long units) { return int(8 * ((units + 7) / 8)); }
+
 // ------------------------------------------------------------------ P1
 template <int N, int DT>
 __global__ void __launch_bounds__((Cfg<N, DT>::LC * Cfg<N, DT>::T))
-p1_r2c(const typename Cfg<N, DT>::Io* __restrict__ rho, Work<DT> w1,
-       const cx<typename Cfg<N, DT>::Real>* __restrict__ tw) {
+p1_r2c(const Batch<DT> bt) {
     using C = Cfg<N, DT>;
     using Real = typename C::Real;
     using F = TeamFFT<N, C::T, Real, -1, false>;
+    constexpr int units = N * N / C::LC;  // per problem
     extern __shared__ __align__(16) unsigned char smem[];
     cx<Real>* sb = reinterpret_cast<cx<Real>*>(smem);
+    const int ug = xcd_unit();
+    if (ug >= bt.count * units) return;
+    const Prob<DT>& P = bt.p[ug / units];
+    const Work<DT> w1 = P.w1;
+    const cx<Real>* __restrict__ tw = P.tw;
     const int t = threadIdx.x % C::T, ln = threadIdx.x / C::T;
-    const size_t line = size_t(blockIdx.x) * C::LC + ln;
-    const typename C::Io* x = rho + line * N;
+    const size_t line = size_t(ug % units) * C::LC + ln;
+    const typename C::Io* x = P.rho + line * N;
 
     // z[j] = x[2j] + i x[2j+1]; zero for j >= n/2 (the padding)
     cx<Real> d[F::E];
@@ -137,31 +174,28 @@ p1_r2c(const typename Cfg<N, DT>::Io* __restrict__ rho, Work<DT> w1,
     }
 }
 
-// Workgroup ids are dealt to the XCDs round robin; give each XCD a contiguous
-// run of units so neighbouring tiles (which may share 128-byte lines) meet in
-// the same L2.
-__device__ __forceinline__ int xcd_unit() {
-    const int g = blockIdx.x;
-    return (g % 8) * (gridDim.x / 8) + g / 8;
-}
-
 // ------------------------------------------------------------------ P2
 // Unit = (i0, tile of B columns k2).  Both outputs of a line (DFT_n of x and
 // of x w^j) are computed in lockstep from the same loads.
 template <int N, int DT, int B, int TT>
 __global__ void __launch_bounds__((B * TT))
-p2_fwd(Work<DT> w1, Work<DT> w2, const cx<typename Cfg<N, DT>::Real>* __restrict__ tw, int units) {
+p2_fwd(const Batch<DT> bt) {
     using C = Cfg<N, DT>;
     using Real = typename C::Real;
     using F = TeamFFT<N, TT, Real, -1, false>;
     using WI = W2Index<N>;
     constexpr int E = F::E;
     constexpr int tiles = N / B;
+    constexpr int units = N * tiles;  // per problem
     extern __shared__ __align__(16) unsigned char smem[];
     cx<Real>* sb = reinterpret_cast<cx<Real>*>(smem);
     cx<Real>* stw = sb + 2 * B * N;
-    const int u = xcd_unit();
-    if (u >= units) return;
+    const int ug = xcd_unit();
+    if (ug >= bt.count * units) return;
+    const Prob<DT>& P = bt.p[ug / units];
+    const Work<DT> w1 = P.w1, w2 = P.w2;
+    const cx<Real>* __restrict__ tw = P.tw;
+    const int u = ug % units;
     const int i0 = u / tiles, tile = u % tiles;
     const int c = threadIdx.x % B, t = threadIdx.x / B;
     const int k2 = tile * B + c;
@@ -201,23 +235,27 @@ p2_fwd(Work<DT> w1, Work<DT> w2, const cx<typename Cfg<N, DT>::Real>* __restrict
 // Column 0 (the packed k2 = 0 / k2 = n pair) is left to p3_col0.
 template <int N, int DT, int B, int TT>
 __global__ void __launch_bounds__((B * TT))
-p3_conv(Work<DT> w2, const typename Cfg<N, DT>::Kt* __restrict__ K,
-        const cx<typename Cfg<N, DT>::Real>* __restrict__ tw, int items) {
+p3_conv(const Batch<DT> bt) {
     using C = Cfg<N, DT>;
     using Real = typename C::Real;
     using Ff = TeamFFT<N, TT, Real, -1, false>;
     using Fi = TeamFFT<N, TT, Real, +1, true>;
     constexpr int E = Ff::E;
     constexpr int tiles = N / B;
+    constexpr int units = 2 * N * tiles;   // per problem: rows k1 and M-k1 of each (pair, tile)
     constexpr size_t s0 = W2Index<N>::s0;  // stride of i0 in W2
     extern __shared__ __align__(16) unsigned char smem[];
     cx<Real>* sb = reinterpret_cast<cx<Real>*>(smem);
     cx<Real>* stw = sb + 2 * B * N;
 
-    const int g = blockIdx.x;
-    const int u = (g % 8) * (gridDim.x / 8) + g / 8;
+    const int ug = xcd_unit();
+    if (ug >= bt.count * units) return;  // whole workgroup
+    const Prob<DT>& P = bt.p[ug / units];
+    const Work<DT> w2 = P.w2;
+    const typename C::Kt* __restrict__ K = P.K;
+    const cx<Real>* __restrict__ tw = P.tw;
+    const int u = ug % units;
     const int item = u >> 1, set = u & 1;
-    if (item >= items) return;  // whole workgroup
     const int q = item / tiles, tile = item % tiles;
     const int k1 = set == 0 ? q : (q == 0 ? N : 2 * N - q);
     const int kt1 = k1 <= N ? k1 : 2 * N - k1;
@@ -272,8 +310,7 @@ p3_conv(Work<DT> w2, const typename Cfg<N, DT>::Kt* __restrict__ K,
 // pairs with itself, as does row n).
 template <int N, int DT>
 __global__ void __launch_bounds__((2 * Cfg<N, DT>::T))
-p3_col0(Work<DT> w2, const typename Cfg<N, DT>::Kt* __restrict__ K,
-        const typename Cfg<N, DT>::Kt* __restrict__ Kb, const cx<typename Cfg<N, DT>::Real>* __restrict__ tw) {
+p3_col0(const Batch<DT> bt) {
     using C = Cfg<N, DT>;
     using Real = typename C::Real;
     using Ff = TeamFFT<N, C::T, Real, -1, false>;
@@ -282,9 +319,15 @@ p3_col0(Work<DT> w2, const typename Cfg<N, DT>::Kt* __restrict__ K,
     extern __shared__ __align__(16) unsigned char smem[];
     cx<Real>* sb = reinterpret_cast<cx<Real>*>(smem);
 
+    if (int(blockIdx.x) >= bt.count * N) return;
+    const Prob<DT>& P = bt.p[blockIdx.x / N];
+    const Work<DT> w2 = P.w2;
+    const typename C::Kt* __restrict__ K = P.K;
+    const typename C::Kt* __restrict__ Kb = P.Kb;
+    const cx<Real>* __restrict__ tw = P.tw;
     const int set = threadIdx.x & 1;
     const int t = threadIdx.x >> 1;
-    const int q = blockIdx.x;
+    const int q = blockIdx.x % N;
     const int k1 = set == 0 ? q : (q == 0 ? N : 2 * N - q);
     const int kt1 = (q == 0) ? (set ? N : 0) : q;
     const int partner = (q == 0) ? set : 1 - set;
@@ -331,18 +374,23 @@ p3_col0(Work<DT> w2, const typename Cfg<N, DT>::Kt* __restrict__ K,
 // inverted in lockstep and combined as y = y_even + w^-j y_odd.
 template <int N, int DT, int B, int TT>
 __global__ void __launch_bounds__((B * TT))
-p4_inv(Work<DT> w2, Work<DT> w1, const cx<typename Cfg<N, DT>::Real>* __restrict__ tw, int units) {
+p4_inv(const Batch<DT> bt) {
     using C = Cfg<N, DT>;
     using Real = typename C::Real;
     using F = TeamFFT<N, TT, Real, +1, false>;
     using WI = W2Index<N>;
     constexpr int E = F::E;
     constexpr int tiles = N / B;
+    constexpr int units = N * tiles;  // per problem
     extern __shared__ __align__(16) unsigned char smem[];
     cx<Real>* sb = reinterpret_cast<cx<Real>*>(smem);
     cx<Real>* stw = sb + 2 * B * N;
-    const int u = xcd_unit();
-    if (u >= units) return;
+    const int ug = xcd_unit();
+    if (ug >= bt.count * units) return;
+    const Prob<DT>& P = bt.p[ug / units];
+    const Work<DT> w1 = P.w1, w2 = P.w2;
+    const cx<Real>* __restrict__ tw = P.tw;
+    const int u = ug % units;
     const int i0 = u / tiles, tile = u % tiles;
     const int c = threadIdx.x % B, t = threadIdx.x / B;
     const int k2 = tile * B + c;
@@ -368,15 +416,22 @@ p4_inv(Work<DT> w2, Work<DT> w1, const cx<typename Cfg<N, DT>::Real>* __restrict
 // ------------------------------------------------------------------ P5
 template <int N, int DT>
 __global__ void __launch_bounds__((Cfg<N, DT>::LC * Cfg<N, DT>::T))
-p5_c2r(Work<DT> w1, typename Cfg<N, DT>::Io* __restrict__ u, const cx<typename Cfg<N, DT>::Real>* __restrict__ tw) {
+p5_c2r(const Batch<DT> bt) {
     using C = Cfg<N, DT>;
     using Real = typename C::Real;
     using Io = typename C::Io;
     using F = TeamFFT<N, C::T, Real, +1, false>;
+    constexpr int units = N * N / C::LC;  // per problem
     extern __shared__ __align__(16) unsigned char smem[];
     cx<Real>* sb = reinterpret_cast<cx<Real>*>(smem);
+    const int ug = xcd_unit();
+    if (ug >= bt.count * units) return;
+    const Prob<DT>& P = bt.p[ug / units];
+    const Work<DT> w1 = P.w1;
+    Io* __restrict__ u = P.u;
+    const cx<Real>* __restrict__ tw = P.tw;
     const int t = threadIdx.x % C::T, ln = threadIdx.x / C::T;
-    const size_t line = size_t(blockIdx.x) * C::LC + ln;
+    const size_t line = size_t(ug % units) * C::LC + ln;
     const size_t base = line * N;
 
     // Y[k] = (V[k] + conj V[n-k]) + i (V[k] - conj V[n-k]) w^-k; V[0], V[n] real and packed
@@ -413,80 +468,91 @@ inline bool allow_lds(const void* fn, size_t bytes) {
     return hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, int(bytes)) == hipSuccess;
 }
 
+// Enqueue the six kernels of one solve for bt.count problems of size N.
 template <int N, int DT>
-hipError_t solve_n(const psn_plan* p, const void* rho_, void* u_, hipStream_t s, hipEvent_t* ev) {
+hipError_t solve_n(const Batch<DT>& bt, hipStream_t s, hipEvent_t* ev) {
     using C = Cfg<N, DT>;
-    using Real = typename C::Real;
-    using Io = typename C::Io;
-    using Kt = typename C::Kt;
-    const Io* rho = static_cast<const Io*>(rho_);
-    Io* u = static_cast<Io*>(u_);
-    const cx<Real>* tw = static_cast<const cx<Real>*>(p->tw);
-    const Kt* K = static_cast<const Kt*>(p->K);
-    const Kt* Kb = static_cast<const Kt*>(p->Kb);
-    Work<DT> w1, w2;
-    if constexpr (DT == DT_SPLIT) {
-        w1 = {static_cast<cx<float>*>(p->W1), static_cast<uint32_t*>(p->W1lo)};
-        w2 = {static_cast<cx<float>*>(p->W2), static_cast<uint32_t*>(p->W2lo)};
-    } else {
-        w1 = {static_cast<cx<Real>*>(p->W1)};
-        w2 = {static_cast<cx<Real>*>(p->W2)};
-    }
     const size_t lds_rows = size_t(C::LC) * C::NP * C::CX;
     const size_t lds_cols = (size_t(2) * C::BS * N + 2 * N) * C::CX;
-    const int units24 = N * (N / C::BS);
-    const int grid24 = 8 * ((units24 + 7) / 8);
-    static const bool lds24_ok = allow_lds(reinterpret_cast<const void*>(&p2_fwd<N, DT, C::BS, C::T24>), lds_cols) &&
-                                 allow_lds(reinterpret_cast<const void*>(&p4_inv<N, DT, C::BS, C::T24>), lds_cols);
-    if (!lds24_ok) return hipErrorInvalidConfiguration;
     const size_t lds_p3 = (size_t(2) * C::BP3 * N + 2 * N) * C::CX;
     const size_t lds_c0 = size_t(2) * N * C::CX;
-    const int items = N * (N / C::BP3);
-    const int grid_p3 = 8 * ((2 * items + 7) / 8);
-    static const bool lds_ok = allow_lds(reinterpret_cast<const void*>(&p3_conv<N, DT, C::BP3, C::T3>), lds_p3);
+    static const bool lds_ok = allow_lds(reinterpret_cast<const void*>(&p2_fwd<N, DT, C::BS, C::T24>), lds_cols) &&
+                               allow_lds(reinterpret_cast<const void*>(&p4_inv<N, DT, C::BS, C::T24>), lds_cols) &&
+                               allow_lds(reinterpret_cast<const void*>(&p3_conv<N, DT, C::BP3, C::T3>), lds_p3);
     if (!lds_ok) return hipErrorInvalidConfiguration;
-
+    const long cnt = bt.count;
     auto mark = [&](int i) {
         if (ev) (void)hipEventRecord(ev[i], s);
     };
     mark(0);
-    hipLaunchKernelGGL((p1_r2c<N, DT>), dim3(N * N / C::LC), dim3(C::LC * C::T), lds_rows, s, rho, w1, tw);
+    hipLaunchKernelGGL((p1_r2c<N, DT>), dim3(xcd_grid(cnt * N * N / C::LC)), dim3(C::LC * C::T), lds_rows, s, bt);
     mark(1);
-    hipLaunchKernelGGL((p2_fwd<N, DT, C::BS, C::T24>), dim3(grid24), dim3(C::BS * C::T24), lds_cols, s, w1, w2, tw,
-                       units24);
+    hipLaunchKernelGGL((p2_fwd<N, DT, C::BS, C::T24>), dim3(xcd_grid(cnt * N * (N / C::BS))), dim3(C::BS * C::T24),
+                       lds_cols, s, bt);
     mark(2);
-    hipLaunchKernelGGL((p3_conv<N, DT, C::BP3, C::T3>), dim3(grid_p3), dim3(C::BP3 * C::T3), lds_p3, s, w2, K, tw,
-                       items);
-    hipLaunchKernelGGL((p3_col0<N, DT>), dim3(N), dim3(2 * C::T), lds_c0, s, w2, K, Kb, tw);
+    hipLaunchKernelGGL((p3_conv<N, DT, C::BP3, C::T3>), dim3(xcd_grid(cnt * 2 * N * (N / C::BP3))),
+                       dim3(C::BP3 * C::T3), lds_p3, s, bt);
+    hipLaunchKernelGGL((p3_col0<N, DT>), dim3(cnt * N), dim3(2 * C::T), lds_c0, s, bt);
     mark(3);
-    hipLaunchKernelGGL((p4_inv<N, DT, C::BS, C::T24>), dim3(grid24), dim3(C::BS * C::T24), lds_cols, s, w2, w1, tw,
-                       units24);
+    hipLaunchKernelGGL((p4_inv<N, DT, C::BS, C::T24>), dim3(xcd_grid(cnt * N * (N / C::BS))), dim3(C::BS * C::T24),
+                       lds_cols, s, bt);
     mark(4);
-    hipLaunchKernelGGL((p5_c2r<N, DT>), dim3(N * N / C::LC), dim3(C::LC * C::T), lds_rows, s, w1, u, tw);
+    hipLaunchKernelGGL((p5_c2r<N, DT>), dim3(xcd_grid(cnt * N * N / C::LC)), dim3(C::LC * C::T), lds_rows, s, bt);
     mark(5);
     return hipGetLastError();
 }
 
 template <int DT>
-hipError_t solve_dt(const psn_plan* p, const void* rho, void* u, hipStream_t s, hipEvent_t* ev) {
-    switch (p->n) {
-#define PSN_CASE(NN) \
-    case NN: return solve_n<NN, DT>(p, rho, u, s, ev);
-        PSN_FOR_EACH_SIZE(PSN_CASE)
-#undef PSN_CASE
-        default: return hipErrorInvalidValue;
+Prob<DT> prob_of(const psn_host::Slot& sl) {
+    using Real = typename Prec<DT>::Real;
+    using Io = typename Prec<DT>::Io;
+    using Kt = typename Prec<DT>::Kt;
+    Prob<DT> pr{};
+    pr.rho = static_cast<const Io*>(sl.rho);
+    pr.u = static_cast<Io*>(sl.u);
+    if constexpr (DT == DT_SPLIT) {
+        pr.w1 = {static_cast<cx<float>*>(sl.W1), static_cast<uint32_t*>(sl.W1lo)};
+        pr.w2 = {static_cast<cx<float>*>(sl.W2), static_cast<uint32_t*>(sl.W2lo)};
+    } else {
+        pr.w1 = {static_cast<cx<Real>*>(sl.W1)};
+        pr.w2 = {static_cast<cx<Real>*>(sl.W2)};
     }
+    pr.K = static_cast<const Kt*>(sl.plan->K);
+    pr.Kb = static_cast<const Kt*>(sl.plan->Kb);
+    pr.tw = static_cast<const cx<Real>*>(sl.plan->tw);
+    return pr;
+}
+
+// Slots [first, first + count) share n and precision.
+template <int DT>
+hipError_t solve_group(const psn_host::Slot* slots, int count, hipStream_t s, hipEvent_t* ev) {
+    for (int base = 0; base < count; base += kMaxBatch) {
+        Batch<DT> bt{};
+        bt.count = count - base < kMaxBatch ? count - base : kMaxBatch;
+        for (int i = 0; i < bt.count; ++i) bt.p[i] = prob_of<DT>(slots[base + i]);
+        hipError_t e = hipErrorInvalidValue;
+        switch (slots[0].plan->n) {
+#define PSN_CASE(NN) \
+    case NN: e = solve_n<NN, DT>(bt, s, ev); break;
+            PSN_FOR_EACH_SIZE(PSN_CASE)
+#undef PSN_CASE
+            default: break;
+        }
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 }  // namespace psn
 
 namespace psn_host {
 
-hipError_t launch_solve(const psn_plan* p, const void* rho, void* u, hipStream_t stream, hipEvent_t* ev) {
-    switch (p->dtype) {
-        case PSN_F64: return psn::solve_dt<psn::DT_F64>(p, rho, u, stream, ev);
-        case PSN_F32: return psn::solve_dt<psn::DT_F32>(p, rho, u, stream, ev);
-        case PSN_SPLIT: return psn::solve_dt<psn::DT_SPLIT>(p, rho, u, stream, ev);
+hipError_t launch_group(const Slot* slots, int count, hipStream_t stream, hipEvent_t* ev) {
+    if (count <= 0) return hipSuccess;
+    switch (slots[0].plan->dtype) {
+        case PSN_F64: return psn::solve_group<psn::DT_F64>(slots, count, stream, ev);
+        case PSN_F32: return psn::solve_group<psn::DT_F32>(slots, count, stream, ev);
+        case PSN_SPLIT: return psn::solve_group<psn::DT_SPLIT>(slots, count, stream, ev);
     }
     return hipErrorInvalidValue;
 }

@@ -5,6 +5,8 @@
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -139,6 +141,54 @@ void free_device(psn_plan* p) {
 
 bool is_real_dtype(int d) { return d == PSN_F64 || d == PSN_F32 || d == PSN_SPLIT; }
 
+size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
+
+// workspace bytes of one solve: W1 (n^3 complex), W2 (2 n^3 complex), and the
+// low parts of the split format
+size_t slot_bytes(const psn_plan* p) {
+    const size_t n3 = size_t(p->n) * p->n * p->n;
+    const size_t wb = p->dtype == PSN_SPLIT ? 8 : psn_host::elem_bytes(p->dtype);
+    size_t b = align256(n3 * wb) + align256(2 * n3 * wb);
+    if (p->dtype == PSN_SPLIT) b += align256(n3 * 4) + align256(2 * n3 * 4);
+    return b;
+}
+
+psn_host::Slot own_slot(const psn_plan* p, const void* rho, void* u) {
+    return psn_host::Slot{p, rho, u, p->W1, p->W2, p->W1lo, p->W2lo};
+}
+
+psn_host::Slot arena_slot(const psn_plan* p, const void* rho, void* u, char* base) {
+    const size_t n3 = size_t(p->n) * p->n * p->n;
+    const size_t wb = p->dtype == PSN_SPLIT ? 8 : psn_host::elem_bytes(p->dtype);
+    psn_host::Slot sl{p, rho, u, nullptr, nullptr, nullptr, nullptr};
+    sl.W1 = base;
+    base += align256(n3 * wb);
+    sl.W2 = base;
+    base += align256(2 * n3 * wb);
+    if (p->dtype == PSN_SPLIT) {
+        sl.W1lo = base;
+        base += align256(n3 * 4);
+        sl.W2lo = base;
+    }
+    return sl;
+}
+
+// Per-device state of batched solves: the workspace arena (grown on demand,
+// held until the process ends) and the captured graphs keyed by the argument
+// list.  Growing the arena synchronises the device.
+struct BatchCache {
+    void* arena = nullptr;
+    size_t arena_bytes = 0;
+    hipStream_t capture = nullptr;
+    std::map<std::vector<const void*>, hipGraphExec_t> graphs;
+    void clear_graphs() {
+        for (auto& g : graphs) (void)hipGraphExecDestroy(g.second);
+        graphs.clear();
+    }
+};
+std::mutex g_batch_mutex;
+std::map<int, BatchCache> g_batch;
+
 }  // namespace
 
 namespace psn_host {
@@ -265,7 +315,8 @@ psn_status psn_solve(psn_plan* p, const void* rho, void* u, void* stream) {
     if (!hip_ok(hipGetDevice(&dev), "hipGetDevice")) return PSN_EDEVICE;
     if (dev != p->device) return PSN_EINVAL;
     (void)hipGetLastError();
-    if (!hip_ok(psn_host::launch_solve(p, rho, u, static_cast<hipStream_t>(stream)), "solve launch"))
+    const psn_host::Slot sl = own_slot(p, rho, u);
+    if (!hip_ok(psn_host::launch_group(&sl, 1, static_cast<hipStream_t>(stream)), "solve launch"))
         return PSN_EDEVICE;
     return PSN_OK;
 }
@@ -285,7 +336,8 @@ psn_status psn_solve_timed(psn_plan* p, const void* rho, void* u, void* stream, 
             return PSN_EDEVICE;
         }
     hipStream_t s = static_cast<hipStream_t>(stream);
-    bool ok = hip_ok(psn_host::launch_solve(p, rho, u, s, ev), "solve launch") &&
+    const psn_host::Slot sl = own_slot(p, rho, u);
+    bool ok = hip_ok(psn_host::launch_group(&sl, 1, s, ev), "solve launch") &&
               hip_ok(hipStreamSynchronize(s), "hipStreamSynchronize");
     for (int i = 0; ok && i < 5; ++i) {
         float ms = 0.f;
@@ -299,14 +351,78 @@ psn_status psn_solve_timed(psn_plan* p, const void* rho, void* u, void* stream, 
 psn_status psn_solve_batched(int count, psn_plan* const* plans, const void* const* rho, void* const* u,
                              void* stream) {
     if (count < 0 || (count > 0 && (!plans || !rho || !u))) return PSN_EINVAL;
+    int dev = -1;
     for (int i = 0; i < count; ++i) {
         if (!plans[i] || !rho[i] || !u[i]) return PSN_EINVAL;
         if (!plans[i]->built) return PSN_ESTATE;
     }
+    if (count == 0) return PSN_OK;
+    g_last_error.clear();
+    (void)hipGetLastError();
+    if (!hip_ok(hipGetDevice(&dev), "hipGetDevice")) return PSN_EDEVICE;
+    for (int i = 0; i < count; ++i)
+        if (plans[i]->device != dev) return PSN_EINVAL;
+    std::lock_guard<std::mutex> lock(g_batch_mutex);
+    BatchCache& bc = g_batch[dev];
+
+    // workspace: one region per entry in the device's batch arena
+    std::vector<size_t> off(count);
+    size_t need = 0;
     for (int i = 0; i < count; ++i) {
-        const psn_status st = psn_solve(plans[i], rho[i], u[i], stream);
-        if (st != PSN_OK) return st;
+        off[i] = need;
+        need += slot_bytes(plans[i]);
     }
+    if (need > bc.arena_bytes) {
+        // the old arena may still be in use by earlier batches on any stream
+        if (bc.arena && !hip_ok(hipDeviceSynchronize(), "hipDeviceSynchronize")) return PSN_EDEVICE;
+        bc.clear_graphs();
+        if (bc.arena) (void)hipFree(bc.arena);
+        bc.arena = nullptr;
+        bc.arena_bytes = 0;
+        if (!hip_ok(hipMalloc(&bc.arena, need), "hipMalloc (batch arena)")) return PSN_ENOMEM;
+        bc.arena_bytes = need;
+    }
+
+    // the launch sequence is captured once per argument list and replayed
+    std::vector<const void*> key;
+    key.reserve(3 * count);
+    for (int i = 0; i < count; ++i) {
+        key.push_back(plans[i]);
+        key.push_back(rho[i]);
+        key.push_back(u[i]);
+    }
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    auto it = bc.graphs.find(key);
+    if (it == bc.graphs.end()) {
+        // group entries by (n, precision), keeping the order within a group
+        std::map<std::pair<int, int>, std::vector<psn_host::Slot>> groups;
+        for (int i = 0; i < count; ++i) {
+            const psn_plan* p = plans[i];
+            groups[{p->n, p->dtype}].push_back(arena_slot(p, rho[i], u[i], static_cast<char*>(bc.arena) + off[i]));
+        }
+        if (!bc.capture && !hip_ok(hipStreamCreateWithFlags(&bc.capture, hipStreamNonBlocking), "hipStreamCreate"))
+            return PSN_EDEVICE;
+        if (!hip_ok(hipStreamBeginCapture(bc.capture, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture"))
+            return PSN_EDEVICE;
+        hipError_t le = hipSuccess;
+        for (auto& g : groups) {
+            le = psn_host::launch_group(g.second.data(), int(g.second.size()), bc.capture);
+            if (le != hipSuccess) break;
+        }
+        hipGraph_t graph = nullptr;
+        const hipError_t ee = hipStreamEndCapture(bc.capture, &graph);
+        if (!hip_ok(le, "batch launch (capture)") || !hip_ok(ee, "hipStreamEndCapture")) {
+            if (graph) (void)hipGraphDestroy(graph);
+            return PSN_EDEVICE;
+        }
+        hipGraphExec_t exec = nullptr;
+        const hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (!hip_ok(ie, "hipGraphInstantiate")) return PSN_EDEVICE;
+        if (bc.graphs.size() >= 16) bc.clear_graphs();
+        it = bc.graphs.emplace(key, exec).first;
+    }
+    if (!hip_ok(hipGraphLaunch(it->second, s), "hipGraphLaunch")) return PSN_EDEVICE;
     return PSN_OK;
 }
 
@@ -378,6 +494,21 @@ psn_status psn_kernel_download(const psn_plan* p, double* octant) {
 
 void psn_plan_destroy(psn_plan* p) {
     if (!p) return;
+    {
+        // captured batches that reference this plan's device arrays go too
+        std::lock_guard<std::mutex> lock(g_batch_mutex);
+        for (auto& dc : g_batch)
+            for (auto it = dc.second.graphs.begin(); it != dc.second.graphs.end();) {
+                bool uses = false;
+                for (size_t i = 0; i < it->first.size(); i += 3) uses |= it->first[i] == p;
+                if (uses) {
+                    (void)hipGraphExecDestroy(it->second);
+                    it = dc.second.graphs.erase(it);
+                } else {
+                    ++it;
+                }
+            }
+    }
     free_device(p);
     delete p;
 }

@@ -195,3 +195,69 @@ def test_n512_mixture_full_size(dtype):
         _cache512["ref"] = O.solve(rho, O.half_spectrum(O.kernel_spectrum(mix.box, 1e-12)))
     u = gpu_solve(psn, torch, 512, 12.0, dtype, _cache512["rho"])
     assert max_rel(u, _cache512["ref"]) <= TOL[dtype]
+
+
+def _batch_case(torch, mixes, dtype):
+    plans, rhos, refs, cache = [], [], [], {}
+    for mix in mixes:
+        n, L = mix.box.n[0], mix.box.b[0]
+        if (n, L) not in cache:
+            cache[(n, L)] = psn.Plan(n, L, 1e-12, dtype).build()
+        plans.append(cache[(n, L)])
+        rho = W.mixture_density(mix)
+        rhos.append(torch.from_numpy(rho).to("cuda", plans[-1].io_dtype()))
+        refs.append(O.solve(rho, oracle_symbol(n, L)))
+    return plans, rhos, refs
+
+
+def test_batched_repeated_plan_graph_replay_and_chunking():
+    """40 problems of one size on ONE plan (more than one launch table of 32),
+    replayed from the captured graph with new input values."""
+    torch = torch_cuda()
+    n, L = 32, 2.5
+    plan = psn.Plan(n, L, 1e-12, "f32").build()
+    sym = oracle_symbol(n, L)
+    rng = np.random.default_rng(17)
+    rhos_np = [_mix(n, L, 200 + i) for i in range(40)]
+    rhos = [torch.from_numpy(r).to("cuda", torch.float32) for r in rhos_np]
+    outs = [torch.empty_like(r) for r in rhos]
+    psn.solve_batched([plan] * 40, rhos, outs)
+    torch.cuda.synchronize()
+    for u, r in zip(outs, rhos_np):
+        assert max_rel(u.double().cpu().numpy(), O.solve(r, sym)) <= TOL["f32"]
+    # same pointers, new values: the replayed graph must see them
+    for i, r in enumerate(rhos):
+        rhos_np[i] = rng.standard_normal((n, n, n)) * np.exp(-np.arange(n) / 8.0)[None, None, :]
+        r.copy_(torch.from_numpy(rhos_np[i]))
+    psn.solve_batched([plan] * 40, rhos, outs)
+    torch.cuda.synchronize()
+    for u, r in zip(outs, rhos_np):
+        assert max_rel(u.double().cpu().numpy(), O.solve(r, sym)) <= 10 * TOL["f32"]
+
+
+def test_batched_mixed_precisions_and_sizes():
+    torch = torch_cuda()
+    mixes = W.config_batched(seed=77, count=6)
+    p32, r32, ref32 = _batch_case(torch, mixes[:3], "f32")
+    p64, r64, ref64 = _batch_case(torch, mixes[3:], "f64")
+    outs = psn.solve_batched(p32 + p64, r32 + r64)
+    torch.cuda.synchronize()
+    for u, ref in zip(outs[:3], ref32):
+        assert max_rel(u.double().cpu().numpy(), ref) <= TOL["f32"]
+    for u, ref in zip(outs[3:], ref64):
+        assert max_rel(u.cpu().numpy(), ref) <= TOL["f64"]
+
+
+def test_batched_after_plan_destroyed():
+    """A captured batch must not outlive the plans it references."""
+    torch = torch_cuda()
+    n, L = 16, 1.5
+    rho_np = _mix(n, L, 9)
+    rho = torch.from_numpy(rho_np).to("cuda", torch.float64)
+    out = torch.empty_like(rho)
+    for _ in range(3):
+        plan = psn.Plan(n, L, 1e-12, "f64").build()
+        psn.solve_batched([plan], [rho], [out])
+        torch.cuda.synchronize()
+        assert max_rel(out.cpu().numpy(), O.solve(rho_np, oracle_symbol(n, L))) <= TOL["f64"]
+        plan.close()
