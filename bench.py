@@ -197,8 +197,14 @@ def main():
         for dt in ("f64", "split"):
             log(f"timing {dt} path")
             p, r, u, ms = time_path(psn, torch, n, L, dt, rho64, max(3, args.steps // 2), args.warmup)
+            pm = np.zeros(5)
+            for _ in range(3):
+                pm += p.solve_timed(r, u)
+            pm /= 3
             extra[dt] = {"ms_per_step": ms, "value": n ** 3 / (ms * 1e-3),
-                         "hbm_frac_whole_solve": p.info()["algorithmic_bytes"] / (ms * 1e-3) / HBM_PEAK}
+                         "hbm_frac_whole_solve": p.info()["algorithmic_bytes"] / (ms * 1e-3) / HBM_PEAK,
+                         "pass_ms": {PASS_NAMES[i]: float(pm[i]) for i in range(5)}}
+            log(f"{dt} pass ms: " + ", ".join(f"{PASS_NAMES[i]}={pm[i]:.3f}" for i in range(5)))
             outs[dt] = u
             log(f"{dt}: {ms:.3f} ms/solve")
             del p, r

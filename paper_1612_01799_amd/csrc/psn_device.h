@@ -199,10 +199,19 @@ struct TwGlobal {
     const cx<Real>* __restrict__ p;
     __device__ __forceinline__ cx<Real> operator()(int m) const { return p[m]; }
 };
+// LDS copy of the table, entries permuted within aligned blocks of 16 (XOR
+// swizzle, no padding): the stage twiddles one wave reads are multiples of a
+// power-of-two stride apart, which would otherwise fall into one bank.
 template <class Real>
 struct TwLds {
-    const cx<Real>* p;
-    __device__ __forceinline__ cx<Real> operator()(int m) const { return p[m]; }
+    cx<Real>* p;
+    static constexpr int slots(int N) { return (2 * N + 15) & ~15; }
+    __device__ __forceinline__ static int at(int m) { return m ^ ((m >> 4) & 15); }
+    __device__ __forceinline__ cx<Real> operator()(int m) const { return p[at(m)]; }
+    // cooperative copy of the 2N-entry table; visible after the next barrier
+    __device__ __forceinline__ void fill(const cx<Real>* __restrict__ tw, int N, int tid, int nthreads) {
+        for (int i = tid; i < 2 * N; i += nthreads) p[at(i)] = tw[i];
+    }
 };
 
 // Adapts a one-value LDS view to the cx[1] interface of TeamFFT::stage.
@@ -311,12 +320,18 @@ struct TeamFFT {
     template <class Lds>
     static __device__ __forceinline__ void run(cx<Real> (&d)[E], int t, const cx<Real>* __restrict__ tw,
                                                Lds& lds) {
+        TwGlobal<Real> g{tw};
+        run1(d, t, g, lds);
+    }
+
+    // single line per thread, any twiddle source
+    template <class Lds, class Tw>
+    static __device__ __forceinline__ void run1(cx<Real> (&d)[E], int t, const Tw& tw, Lds& lds) {
         cx<Real> dd[1][E];
 #pragma unroll
         for (int e = 0; e < E; ++e) dd[0][e] = d[e];
         Single<Lds> l1{lds};
-        TwGlobal<Real> g{tw};
-        stage<0, 1>(dd, t, g, l1);
+        stage<0, 1>(dd, t, tw, l1);
 #pragma unroll
         for (int e = 0; e < E; ++e) d[e] = dd[0][e];
     }

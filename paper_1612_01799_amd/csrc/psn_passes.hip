@@ -43,7 +43,7 @@ constexpr int pick_cols(int N, int bmax, int sets, int cxbytes, int T) {
 
 constexpr int pick_cols_p3(int N, int bmax, int cxbytes, int T) {
     for (int b = bmax; b >= 1; --b)
-        if (N % b == 0 && (2 * b * N + 2 * N) * cxbytes <= kMaxLdsP3 && b * T <= 1024) return b;
+        if (N % b == 0 && (2 * b * N + ((2 * N + 15) & ~15)) * cxbytes <= kMaxLdsP3 && b * T <= 1024) return b;
     return 1;
 }
 
@@ -52,7 +52,7 @@ constexpr int rows_padded(int N) { return N + (N >> 4) + 1; }
 constexpr int pick_lines(int N, int T, int cxbytes) {
     int l = 256 / T;
     if (l < 1) l = 1;
-    while (l > 1 && ((N * N) % l != 0 || l * rows_padded(N) * cxbytes > kMaxLds)) l /= 2;
+    while (l > 1 && ((N * N) % l != 0 || (l * rows_padded(N) + ((2 * N + 15) & ~15)) * cxbytes > kMaxLds)) l /= 2;
     return l;
 }
 
@@ -150,8 +150,10 @@ p1_r2c(const Batch<DT> bt) {
         if (pos < N / 2) d[e] = {Real(x[2 * pos]), Real(x[2 * pos + 1])};
         else d[e] = {Real(0), Real(0)};
     }
+    TwLds<Real> tl{sb + C::LC * C::NP};
+    tl.fill(tw, N, threadIdx.x, C::LC * C::T);
     LdsRows<Real> lds{sb + ln * C::NP};
-    F::run(d, t, tw, lds);
+    F::run1(d, t, tl, lds);
     __syncthreads();
 #pragma unroll
     for (int e = 0; e < F::E; ++e) lds.put(F::out_pos(t, e), d[e]);
@@ -168,7 +170,7 @@ p1_r2c(const Batch<DT> bt) {
             const cx<Real> Zr = conj(lds.get(N - k));
             const cx<Real> Ev = scale(Z + Zr, Real(0.5));
             const cx<Real> Od = rot<-1>(scale(Z - Zr, Real(0.5)));
-            X = Ev + Od * tw[k];
+            X = Ev + Od * tl(k);
         }
         w1.st(line * N + k, X);
     }
@@ -208,11 +210,11 @@ p2_fwd(const Batch<DT> bt) {
         d[0][e] = w1.ld(inb + size_t(pos) * N);
         w[e] = tw[pos];
     }
-    for (int i = threadIdx.x; i < 2 * N; i += B * TT) stw[i] = tw[i];
+    TwLds<Real> tl{stw};
+    tl.fill(tw, N, threadIdx.x, B * TT);  // visible after the first exchange
 #pragma unroll
     for (int e = 0; e < E; ++e) d[1][e] = d[0][e] * w[e];
     LdsCols2<Real> lds{sb, B, c};
-    TwLds<Real> tl{stw};
     F::template run<2>(d, t, tl, lds);
 #pragma unroll
     for (int e = 0; e < E; ++e) {
@@ -279,7 +281,8 @@ p3_conv(const Batch<DT> bt) {
         ke[e] = Real(Krow[size_t(a <= N ? a : 2 * N - a) * N]);
         ko[e] = Real(Krow[size_t(b <= N ? b : 2 * N - b) * N]);
     }
-    for (int i = threadIdx.x; i < 2 * N; i += B * TT) stw[i] = tw[i];  // visible after the first exchange
+    TwLds<Real> tl{stw};
+    tl.fill(tw, N, threadIdx.x, B * TT);  // visible after the first exchange
 
     cx<Real> d[2][E];
 #pragma unroll
@@ -288,7 +291,6 @@ p3_conv(const Batch<DT> bt) {
         d[1][e] = x[e] * w[e];
     }
     LdsCols2<Real> lds{sb, B, c};
-    TwLds<Real> tl{stw};
     Ff::template run<2>(d, t, tl, lds);
 #pragma unroll
     for (int e = 0; e < E; ++e) {
@@ -404,9 +406,9 @@ p4_inv(const Batch<DT> bt) {
         d[1][e] = w2.ld(WI::at(i0, 2 * pos + 1, k2));
         w[e] = tw[F::out_pos(t, e)];
     }
-    for (int i = threadIdx.x; i < 2 * N; i += B * TT) stw[i] = tw[i];
-    LdsCols2<Real> lds{sb, B, c};
     TwLds<Real> tl{stw};
+    tl.fill(tw, N, threadIdx.x, B * TT);  // visible after the first exchange
+    LdsCols2<Real> lds{sb, B, c};
     F::template run<2>(d, t, tl, lds);
 #pragma unroll
     for (int e = 0; e < E; ++e)
@@ -448,8 +450,11 @@ p5_c2r(const Batch<DT> bt) {
             d[e] = (a + b) + rot<+1>(mul_conj(a - b, tw[pos]));
         }
     }
+    TwLds<Real> tl{sb + C::LC * C::NP};
+    tl.fill(tw, N, threadIdx.x, C::LC * C::T);
+    if constexpr (F::S == 1) __syncthreads();
     LdsRows<Real> lds{sb + ln * C::NP};
-    F::run(d, t, tw, lds);
+    F::run1(d, t, tl, lds);
     // z[j] = u[2j] + i u[2j+1]; only j < n/2 lies inside the box
 #pragma unroll
     for (int e = 0; e < F::E; ++e) {
@@ -472,9 +477,10 @@ inline bool allow_lds(const void* fn, size_t bytes) {
 template <int N, int DT>
 hipError_t solve_n(const Batch<DT>& bt, hipStream_t s, hipEvent_t* ev) {
     using C = Cfg<N, DT>;
-    const size_t lds_rows = size_t(C::LC) * C::NP * C::CX;
-    const size_t lds_cols = (size_t(2) * C::BS * N + 2 * N) * C::CX;
-    const size_t lds_p3 = (size_t(2) * C::BP3 * N + 2 * N) * C::CX;
+    constexpr size_t tws = TwLds<typename C::Real>::slots(N);
+    const size_t lds_rows = (size_t(C::LC) * C::NP + tws) * C::CX;
+    const size_t lds_cols = (size_t(2) * C::BS * N + tws) * C::CX;
+    const size_t lds_p3 = (size_t(2) * C::BP3 * N + tws) * C::CX;
     const size_t lds_c0 = size_t(2) * N * C::CX;
     static const bool lds_ok = allow_lds(reinterpret_cast<const void*>(&p2_fwd<N, DT, C::BS, C::T24>), lds_cols) &&
                                allow_lds(reinterpret_cast<const void*>(&p4_inv<N, DT, C::BS, C::T24>), lds_cols) &&
