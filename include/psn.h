@@ -1,8 +1,9 @@
 /*
  * psn.h -- C ABI of the MI355X free-space Poisson solver.
  *
- * Computes u = U * rho with U(x) = 1/(4 pi |x|) on a cube [-L, L]^3 sampled
- * with n points per axis (both end points included, h = 2L/(n-1)), by the
+ * Computes u = U * rho with U(x) = 1/(4 pi |x|) on a box (the cube [-L, L]^3 or
+ * a general [a0,b0] x [a1,b1] x [a2,b2]) sampled with n points per axis (both
+ * end points included, h_q = (b_q - a_q)/(n-1)), by the
  * method of Exl, "A GPU accelerated and error-controlled solver for the
  * unbounded Poisson equation in three dimensions" (arXiv 1612.01799):
  *
@@ -55,13 +56,13 @@ typedef enum {
 typedef struct {
     int n;              /* points per axis */
     int dtype;          /* psn_dtype */
-    double L;           /* half-width of the cube */
+    double L;           /* largest half-width of the box (lambda of section 2; the cube's L) */
     double tol;         /* requested Gaussian-sum relative tolerance eps */
-    double h;           /* grid spacing 2L/(n-1) */
-    double T;           /* kernel truncation n*h (half the padded period) */
-    double period;      /* padded FFT period 2*n*h */
+    double h;           /* grid spacing of axis 0: (b0-a0)/(n-1) */
+    double T;           /* kernel truncation of axis 0: n*h (half the padded period) */
+    double period;      /* padded FFT period of axis 0: 2*n*h */
     double delta;       /* near-zone radius (section 3 heuristic, physical units) */
-    double R;           /* largest distance the Gaussian sum must resolve: 2*sqrt(3)*L */
+    double R;           /* largest distance the Gaussian sum must resolve: the box diagonal */
     double hs;          /* sinc-quadrature step */
     int terms;          /* number of Gaussian-sum terms (S + 1) */
     double eps_achieved;/* max |U_GS/U - 1| on the check grid */
@@ -69,6 +70,9 @@ typedef struct {
     int built;          /* 1 after psn_kernel_build succeeded */
     size_t device_bytes;     /* device memory held by the plan */
     double algorithmic_bytes;/* HBM bytes one solve must move (five pruned passes) */
+    double a[3], b[3];  /* the box [a0,b0] x [a1,b1] x [a2,b2] */
+    double h3[3];       /* grid spacing per axis */
+    double T3[3];       /* kernel truncation per axis */
 } psn_plan_info;
 
 /* Create a plan for an n^3 grid on [-L, L]^3 (the solver construction of the
@@ -78,6 +82,15 @@ typedef struct {
  * and no device memory.  On success *out owns a new plan; on failure *out is
  * set to NULL.  Errors: PSN_EINVAL, PSN_ESIZE, PSN_EFIT. */
 psn_status psn_plan_create(int n, double L, double tol, psn_dtype dtype, psn_plan **out);
+
+/* As psn_plan_create for a general rectangular box [a0,b0] x [a1,b1] x [a2,b2]
+ * (arrays of 3 doubles, b_q > a_q), n points per axis (section 2's general box:
+ * per-axis spacing h_q = (b_q - a_q)/(n-1), per-axis factors of the G-tensor;
+ * delta from the smallest axis and lambda = the largest half-width; the
+ * Gaussian sum resolves distances up to the box diagonal).
+ * Errors: PSN_EINVAL, PSN_ESIZE, PSN_EFIT. */
+psn_status psn_plan_create_box(int n, const double *a, const double *b, double tol, psn_dtype dtype,
+                               psn_plan **out);
 
 /* Build the kernel spectrum on the current device (the G-tensor precomputation
  * of section 3): FP64 mode integrals, correction constants C0 and C2 and the

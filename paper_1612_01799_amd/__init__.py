@@ -44,7 +44,8 @@ class PlanInfo(ctypes.Structure):
         ("delta", ctypes.c_double), ("R", ctypes.c_double), ("hs", ctypes.c_double),
         ("terms", ctypes.c_int), ("eps_achieved", ctypes.c_double), ("C0", ctypes.c_double),
         ("C2", ctypes.c_double), ("built", ctypes.c_int), ("device_bytes", ctypes.c_size_t),
-        ("algorithmic_bytes", ctypes.c_double),
+        ("algorithmic_bytes", ctypes.c_double), ("a", ctypes.c_double * 3), ("b", ctypes.c_double * 3),
+        ("h3", ctypes.c_double * 3), ("T3", ctypes.c_double * 3),
     ]
 
 
@@ -62,6 +63,9 @@ def _load():
     sig = {
         "psn_plan_create": (ctypes.c_int, [ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_int,
                                            ctypes.POINTER(P)]),
+        "psn_plan_create_box": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(ctypes.c_double),
+                                               ctypes.POINTER(ctypes.c_double), ctypes.c_double, ctypes.c_int,
+                                               ctypes.POINTER(P)]),
         "psn_kernel_build": (ctypes.c_int, [P, P]),
         "psn_solve": (ctypes.c_int, [P, P, P, P]),
         "psn_solve_timed": (ctypes.c_int, [P, P, P, P, ctypes.POINTER(ctypes.c_double)]),
@@ -107,15 +111,23 @@ def _stream_handle(stream):
 
 
 class Plan:
-    """One grid geometry: n^3 points on [-L, L]^3, Gaussian-sum tolerance tol."""
+    """One grid geometry: n^3 points on [-L, L]^3 (or on the box a..b when
+    `box=(a, b)` is given, a and b 3-sequences), Gaussian-sum tolerance tol."""
 
-    def __init__(self, n: int, L: float, tol: float = 1e-12, dtype="f32"):
+    def __init__(self, n: int, L: float = None, tol: float = 1e-12, dtype="f32", box=None):
         self._h = ctypes.c_void_p()
         self.n = int(n)
-        self.L = float(L)
         self.dtype = _DTYPES[dtype]
-        _check(_lib.psn_plan_create(self.n, self.L, float(tol), self.dtype, ctypes.byref(self._h)),
-               "psn_plan_create")
+        if box is None:
+            self.L = float(L)
+            _check(_lib.psn_plan_create(self.n, self.L, float(tol), self.dtype, ctypes.byref(self._h)),
+                   "psn_plan_create")
+        else:
+            a = (ctypes.c_double * 3)(*[float(v) for v in box[0]])
+            b = (ctypes.c_double * 3)(*[float(v) for v in box[1]])
+            self.L = max(0.5 * (b[q] - a[q]) for q in range(3))
+            _check(_lib.psn_plan_create_box(self.n, a, b, float(tol), self.dtype, ctypes.byref(self._h)),
+                   "psn_plan_create_box")
 
     # -- setup
     def build(self, stream=None) -> "Plan":
@@ -153,7 +165,11 @@ class Plan:
     def info(self) -> dict:
         inf = PlanInfo()
         _check(_lib.psn_plan_query(self._h, ctypes.byref(inf)), "psn_plan_query")
-        return {f: getattr(inf, f) for f, _ in PlanInfo._fields_}
+        out = {}
+        for f, _ in PlanInfo._fields_:
+            v = getattr(inf, f)
+            out[f] = tuple(v) if isinstance(v, ctypes.Array) else v
+        return out
 
     def gs_table(self):
         import numpy as np

@@ -13,11 +13,13 @@
     X(8) X(12) X(16) X(24) X(32) X(48) X(64) X(96) X(128) X(160) X(192) X(256) X(320) X(384) X(512)
 
 struct psn_plan {
-    // geometry (section 4 grid; padded period 2nh; truncation T = nh)
+    // geometry (section 4 grid; padded period 2nh; truncation T = nh), per axis
     int n = 0;
-    double L = 0, tol = 0;
+    double L = 0, tol = 0;  // L: largest half-width (lambda of section 2)
     psn_dtype dtype = PSN_F64;
-    double h = 0, T = 0, period = 0, delta = 0, R = 0;
+    double a[3] = {0, 0, 0}, b[3] = {0, 0, 0};
+    double h[3] = {0, 0, 0}, T[3] = {0, 0, 0}, period[3] = {0, 0, 0};
+    double delta = 0, R = 0;
     // Gaussian sum (section 2)
     double hs = 0, gs_err = 0;
     std::vector<double> tau, w;
@@ -56,6 +58,7 @@ hipError_t launch_group(const Slot* slots, int count, hipStream_t stream, hipEve
 
 // Kernel spectrum build on the device (FP64), written into p->K / p->Kb in
 // the plan's storage type, plus C0/C2 into the two doubles at d_c.
+// d_A holds three tables of terms x (n+1) doubles (one per axis).
 hipError_t launch_kernel_build(psn_plan* p, const double* d_tau, const double* d_w, int terms,
                                const double* d_glx, const double* d_glw, double* d_A, double* d_c,
                                hipStream_t stream);

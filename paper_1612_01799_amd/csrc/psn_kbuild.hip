@@ -99,26 +99,28 @@ __global__ void k_correction(const double* __restrict__ tau, const double* __res
     }
 }
 
-// One workgroup per (k0~, k1~); threads run over k2 = 0..n.
+// One workgroup per (k0~, k1~); threads run over k2 = 0..n.  A0, A1, A2 are the
+// mode tables of the three axes (the same table for a cube).
 template <class Kt>
-__global__ void k_assemble(const double* __restrict__ A, const double* __restrict__ w, int terms, int n,
-                           double period, const double* __restrict__ Cc, double scale, Kt* __restrict__ K,
-                           Kt* __restrict__ Kb) {
+__global__ void k_assemble(const double* __restrict__ A0, const double* __restrict__ A1,
+                           const double* __restrict__ A2, const double* __restrict__ w, int terms, int n,
+                           double p0, double p1, double p2, const double* __restrict__ Cc, double scale,
+                           Kt* __restrict__ K, Kt* __restrict__ Kb) {
     extern __shared__ double cj[];
     __shared__ double edge[2];
     const int kt0 = blockIdx.x, kt1 = blockIdx.y;
     const int np1 = n + 1;
     for (int j = threadIdx.x; j < terms; j += blockDim.x)
-        cj[j] = w[j] * A[size_t(j) * np1 + kt0] * A[size_t(j) * np1 + kt1];
+        cj[j] = w[j] * A0[size_t(j) * np1 + kt0] * A1[size_t(j) * np1 + kt1];
     __syncthreads();
     const double C0 = Cc[0], C2 = Cc[1];
-    const double kb = 2.0 * kPi / period;
-    const double q01 = kb * kb * (double(kt0) * kt0 + double(kt1) * kt1);
+    const double b0 = 2.0 * kPi * kt0 / p0, b1 = 2.0 * kPi * kt1 / p1, b2 = 2.0 * kPi / p2;
+    const double q01 = b0 * b0 + b1 * b1;
     const size_t row = (size_t(kt1) * np1 + kt0) * n;
     for (int k2 = threadIdx.x; k2 <= n; k2 += blockDim.x) {
         double s = 0.0;
-        for (int j = 0; j < terms; ++j) s = fma(cj[j], A[size_t(j) * np1 + k2], s);
-        const double v = s + C0 - (C2 / 6.0) * (q01 + kb * kb * double(k2) * k2);
+        for (int j = 0; j < terms; ++j) s = fma(cj[j], A2[size_t(j) * np1 + k2], s);
+        const double v = s + C0 - (C2 / 6.0) * (q01 + b2 * b2 * double(k2) * k2);
         if (k2 == 0) edge[0] = v;
         else if (k2 == n) edge[1] = v;
         else K[row + k2] = Kt(scale * v);
@@ -137,18 +139,33 @@ namespace psn_host {
 hipError_t launch_kernel_build(psn_plan* p, const double* d_tau, const double* d_w, int terms, const double* d_glx,
                                const double* d_glw, double* d_A, double* d_c, hipStream_t s) {
     const int n = p->n;
-    hipLaunchKernelGGL(psn::k_modes, dim3((n + 1 + 127) / 128, terms), dim3(128), 0, s, d_tau, n, p->T, p->period,
-                       d_glx, d_glw, d_A);
+    const size_t tab = size_t(terms) * (n + 1);
+    // one mode table per distinct axis length
+    const double* A[3];
+    for (int q = 0; q < 3; ++q) {
+        int same = -1;
+        for (int r = 0; r < q; ++r)
+            if (p->T[r] == p->T[q] && p->period[r] == p->period[q]) same = r;
+        if (same >= 0) {
+            A[q] = A[same];
+            continue;
+        }
+        A[q] = d_A + q * tab;
+        hipLaunchKernelGGL(psn::k_modes, dim3((n + 1 + 127) / 128, terms), dim3(128), 0, s, d_tau, n, p->T[q],
+                           p->period[q], d_glx, d_glw, d_A + q * tab);
+    }
     hipLaunchKernelGGL(psn::k_correction, dim3(1), dim3(256), 0, s, d_tau, d_w, terms, p->delta, d_c);
     const double M = 2.0 * n;
     const double scale = 1.0 / (M * M * M);
     const size_t lds = size_t(terms) * sizeof(double);
     if (p->dtype == PSN_F32) {
-        hipLaunchKernelGGL(psn::k_assemble<float>, dim3(n + 1, n + 1), dim3(256), lds, s, d_A, d_w, terms, n,
-                           p->period, d_c, scale, static_cast<float*>(p->K), static_cast<float*>(p->Kb));
+        hipLaunchKernelGGL(psn::k_assemble<float>, dim3(n + 1, n + 1), dim3(256), lds, s, A[0], A[1], A[2], d_w,
+                           terms, n, p->period[0], p->period[1], p->period[2], d_c, scale, static_cast<float*>(p->K),
+                           static_cast<float*>(p->Kb));
     } else {
-        hipLaunchKernelGGL(psn::k_assemble<double>, dim3(n + 1, n + 1), dim3(256), lds, s, d_A, d_w, terms, n,
-                           p->period, d_c, scale, static_cast<double*>(p->K), static_cast<double*>(p->Kb));
+        hipLaunchKernelGGL(psn::k_assemble<double>, dim3(n + 1, n + 1), dim3(256), lds, s, A[0], A[1], A[2], d_w,
+                           terms, n, p->period[0], p->period[1], p->period[2], d_c, scale,
+                           static_cast<double*>(p->K), static_cast<double*>(p->Kb));
     }
     return hipGetLastError();
 }

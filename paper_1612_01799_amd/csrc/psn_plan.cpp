@@ -204,32 +204,51 @@ int psn_size_supported(int n) {
     return (n >= 4 && n % 2 == 0 && five_smooth(2L * n) && psn_host::size_compiled(n)) ? 1 : 0;
 }
 
-psn_status psn_plan_create(int n, double L, double tol, psn_dtype dtype, psn_plan** out) {
+psn_status psn_plan_create_box(int n, const double* a, const double* b, double tol, psn_dtype dtype,
+                               psn_plan** out) {
     if (!out) return PSN_EINVAL;
     *out = nullptr;
-    if (!is_real_dtype(dtype) || !(L > 0) || !std::isfinite(L) || !(tol >= 1e-15 && tol <= 1e-4))
-        return PSN_EINVAL;
+    if (!a || !b || !is_real_dtype(dtype) || !(tol >= 1e-15 && tol <= 1e-4)) return PSN_EINVAL;
+    for (int q = 0; q < 3; ++q)
+        if (!std::isfinite(a[q]) || !std::isfinite(b[q]) || !(b[q] > a[q])) return PSN_EINVAL;
     if (!psn_size_supported(n)) return PSN_ESIZE;
     psn_plan* p = new (std::nothrow) psn_plan();
     if (!p) return PSN_ENOMEM;
     p->n = n;
-    p->L = L;
     p->tol = tol;
     p->dtype = dtype;
-    p->h = 2.0 * L / (n - 1);
-    p->T = n * p->h;
-    p->period = 2.0 * n * p->h;
-    // section 3: delta = min_q (b_q - a_q) / (50 n_q) in the standardised frame,
-    // at least 1e-3; the physical radius is lambda (= L) times that.
-    const double delta_std = std::fmax(1e-3, 2.0 * L / (50.0 * n));
-    p->delta = L * delta_std;
-    p->R = 2.0 * std::sqrt(3.0) * L;
+    double lam = 0.0, dmin = 1e300, diag2 = 0.0;
+    for (int q = 0; q < 3; ++q) {
+        const double w = b[q] - a[q];
+        p->a[q] = a[q];
+        p->b[q] = b[q];
+        p->h[q] = w / (n - 1);
+        p->T[q] = n * p->h[q];
+        p->period[q] = 2.0 * n * p->h[q];
+        lam = std::fmax(lam, 0.5 * w);
+        dmin = std::fmin(dmin, w / (50.0 * n));
+        diag2 += w * w;
+    }
+    p->L = lam;
+    // section 3: delta = min_q (b_q - a_q) / (50 n_q) in the standardised
+    // frame, at least 1e-3; the physical radius is lambda times that
+    p->delta = lam * std::fmax(1e-3, dmin);
+    // the Gaussian sum must resolve every distance between two grid points
+    p->R = std::sqrt(diag2);
     if (!fit_gaussian_sum(p)) {
         delete p;
         return PSN_EFIT;
     }
     *out = p;
     return PSN_OK;
+}
+
+psn_status psn_plan_create(int n, double L, double tol, psn_dtype dtype, psn_plan** out) {
+    if (!out) return PSN_EINVAL;
+    *out = nullptr;
+    if (!(L > 0) || !std::isfinite(L)) return PSN_EINVAL;
+    const double a[3] = {-L, -L, -L}, b[3] = {L, L, L};
+    return psn_plan_create_box(n, a, b, tol, dtype, out);
 }
 
 psn_status psn_kernel_build(psn_plan* p, void* stream) {
@@ -278,7 +297,7 @@ psn_status psn_kernel_build(psn_plan* p, void* stream) {
 
     DevBuf d_tau, d_w, d_gl, d_A, d_c;
     if ((st = dev_alloc(&d_tau.p, terms * 8, &tot)) || (st = dev_alloc(&d_w.p, terms * 8, &tot)) ||
-        (st = dev_alloc(&d_gl.p, 32 * 8, &tot)) || (st = dev_alloc(&d_A.p, size_t(terms) * (n + 1) * 8, &tot)) ||
+        (st = dev_alloc(&d_gl.p, 32 * 8, &tot)) || (st = dev_alloc(&d_A.p, 3 * size_t(terms) * (n + 1) * 8, &tot)) ||
         (st = dev_alloc(&d_c.p, 2 * 8, &tot))) {
         free_device(p);
         return st;
@@ -433,9 +452,15 @@ psn_status psn_plan_query(const psn_plan* p, psn_plan_info* info) {
     info->dtype = p->dtype;
     info->L = p->L;
     info->tol = p->tol;
-    info->h = p->h;
-    info->T = p->T;
-    info->period = p->period;
+    info->h = p->h[0];
+    info->T = p->T[0];
+    info->period = p->period[0];
+    for (int q = 0; q < 3; ++q) {
+        info->a[q] = p->a[q];
+        info->b[q] = p->b[q];
+        info->h3[q] = p->h[q];
+        info->T3[q] = p->T[q];
+    }
     info->delta = p->delta;
     info->R = p->R;
     info->hs = p->hs;

@@ -85,6 +85,32 @@ def test_geometry_and_gaussian_sum_match_oracle(n, L, tol):
     assert np.max(np.abs(w / w_o - 1)) <= 1e-14
 
 
+@pytest.mark.parametrize("a,b,n", [((-3, -2, -1), (2, 3.5, 5), 32), ((-3, -2, -2), (1, 3, 4), 16),
+                                   ((-2, -4, -6), (2, 4, 6), 64)])
+def test_box_geometry_matches_oracle(a, b, n):
+    p = psn.Plan(n, box=(a, b), tol=1e-12, dtype="f64")
+    info = p.info()
+    g = O.geometry(W.Box(a, b, (n, n, n)))
+    for q in range(3):
+        assert info["h3"][q] == pytest.approx(g.h[q], rel=1e-15)
+        assert info["T3"][q] == pytest.approx(g.T[q], rel=1e-15)
+        assert info["a"][q] == a[q] and info["b"][q] == b[q]
+    assert info["delta"] == pytest.approx(g.delta, rel=1e-15)
+    assert info["R"] == pytest.approx(g.R, rel=1e-15)
+    assert info["L"] == pytest.approx(g.lam, rel=1e-15)
+    tau_o, _, _ = O.gaussian_sum(1e-12, g.delta, g.R)
+    assert info["terms"] == tau_o.size
+
+
+def test_box_rejects_empty_axes():
+    with pytest.raises(psn.PsnError) as e:
+        psn.Plan(16, box=((0, 0, 0), (1, 0, 1)))
+    assert e.value.status == -1
+    with pytest.raises(psn.PsnError) as e:
+        psn.Plan(16, box=((0, 0, 0), (1, float("nan"), 1)))
+    assert e.value.status == -1
+
+
 def test_solve_before_build_is_a_state_error():
     p = psn.Plan(16, 1.0, 1e-12, "f32")
     lib = psn._lib

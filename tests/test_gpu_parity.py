@@ -40,6 +40,24 @@ def test_kernel_spectrum_matches_oracle(n, dtype):
     assert info["C2"] == pytest.approx(ks.C2, rel=1e-12, abs=1e-24)
 
 
+@pytest.mark.parametrize("dtype", ["f64", "f32", "split"])
+def test_box_kernel_and_solve_match_oracle(dtype):
+    """Rectangular box [-3,2] x [-2,3.5] x [-1,5]: per-axis spacing and modes."""
+    torch = torch_cuda()
+    n = 32
+    box = W.Box((-3.0, -2.0, -1.0), (2.0, 3.5, 5.0), (n, n, n))
+    plan = psn.Plan(n, box=(box.a, box.b), tol=1e-12, dtype=dtype).build()
+    ks = O.kernel_spectrum(box, 1e-12)
+    K = plan.kernel_octant()
+    tol = 1e-13 if dtype != "f32" else 2e-7
+    assert np.max(np.abs(K - ks.octant)) <= tol * abs(ks.octant[0, 0, 0])
+    mix = W.draw_mixture(41, 4, -0.3, 0.6, 0.35, 0.6, 0.5, 1.5, box)
+    rho = W.mixture_density(mix)
+    ref = O.solve(rho, O.half_spectrum(ks))
+    u = gpu_solve(psn, torch, n, None, dtype, rho, plan=plan)
+    assert max_rel(u, ref) <= TOL[dtype]
+
+
 @pytest.mark.parametrize("n", SIZES)
 @pytest.mark.parametrize("dtype", ["f64", "f32", "split"])
 def test_solve_matches_oracle(n, dtype):
@@ -66,15 +84,17 @@ def test_random_density_all_frequencies(dtype):
 
 def _gpu_entries():
     g = PC.load()
-    return [e for e in g["digits"] + g["three_digits"] if e["a"] == [-2, -2, -2] and e["b"] == [2, 2, 2]]
+    return g["digits"] + g["three_digits"]
 
 
 @pytest.mark.parametrize("entry", _gpu_entries(), ids=[PC.name(e) for e in _gpu_entries()])
 def test_paper_tables_on_gpu_fp64(entry):
-    """The printed E of the cube tables, reproduced by the FP64 GPU path."""
+    """The printed E of Tables 1-7 (cubes and rectangular boxes), reproduced by
+    the FP64 GPU path."""
     torch = torch_cuda()
     box, rho, ustar = PC.case(entry)
-    u = gpu_solve(psn, torch, box.n[0], 2.0, "f64", rho, tol=entry.get("eps", 1e-12))
+    plan = psn.Plan(box.n[0], box=(box.a, box.b), tol=entry.get("eps", 1e-12), dtype="f64").build()
+    u = gpu_solve(psn, torch, box.n[0], None, "f64", rho, plan=plan)
     E = O.error_E(u, ustar)
     digits = 4 if entry in PC.load()["digits"] else 3
     assert abs(E - entry["E"]) <= 0.5 * 10 ** (math.floor(math.log10(entry["E"])) - (digits - 1)) * 1.0001
