@@ -24,6 +24,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK = 8.0e12        # MI355X HBM3E, bytes/s
+KERNEL_SOURCES = ("psn_device.h", "psn_passes.h")   # hashed to match a traffic profile to its kernels
 PASS_NAMES = ["P1_r2c_axis2", "P2_fwd_axis1", "P3_fwd_mulK_inv_axis0", "P4_inv_axis1", "P5_c2r_axis2"]
 
 
@@ -56,8 +57,11 @@ def measured_traffic(n, kernel):
     path = os.path.join(ROOT, "profiles", f"solve_n{n}_f32_hbm_traffic.txt")
     if kernel != "P3_fwd_mulK_inv_axis0" or not os.path.exists(path):
         return None
-    src = b"".join(open(os.path.join(ROOT, "paper_1612_01799_amd", "csrc", f), "rb").read()
-                   for f in ("psn_device.h", "psn_passes.hip"))
+    try:
+        src = b"".join(open(os.path.join(ROOT, "paper_1612_01799_amd", "csrc", f), "rb").read()
+                       for f in KERNEL_SOURCES)
+    except OSError:
+        return None
     digest = hashlib.sha256(src).hexdigest()[:16]
     total, recorded = None, None
     for line in open(path):
@@ -261,7 +265,8 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": desc, "n": n, "padded": 2 * n, "path": "f32", "tol": 1e-12},
+        "config": {"workload": desc, "n": n, "padded": 2 * n, "path": "f32", "tol": 1e-12,
+                   "schedule": list(info32["schedule"]), "tuned": bool(info32["tuned"])},
         "roofline": {"bound": "hbm", "kernel": PASS_NAMES[dom], "achieved": achieved / 1e9, "peak": HBM_PEAK / 1e9,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK, "traffic": measured_traffic(n, PASS_NAMES[dom]),
                      "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE/WRITE_SIZE, copy-calibrated)",

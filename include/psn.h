@@ -73,6 +73,8 @@ typedef struct {
     double a[3], b[3];  /* the box [a0,b0] x [a1,b1] x [a2,b2] */
     double h3[3];       /* grid spacing per axis */
     double T3[3];       /* kernel truncation per axis */
+    int schedule[2];    /* tile candidates of the axis-1 passes and of the axis-0 pass */
+    int tuned;          /* 1 if the schedule came from the autotuner */
 } psn_plan_info;
 
 /* Create a plan for an n^3 grid on [-L, L]^3 (the solver construction of the
@@ -95,7 +97,10 @@ psn_status psn_plan_create_box(int n, const double *a, const double *b, double t
 /* Build the kernel spectrum on the current device (the G-tensor precomputation
  * of section 3): FP64 mode integrals, correction constants C0 and C2 and the
  * octant assembly, then conversion to the plan's storage type; also allocates
- * the solve workspace.  Synchronises `stream` before returning.  Idempotent.
+ * the solve workspace.  Then picks the tile schedule of the strided passes:
+ * each has three compiled candidates, timed once per (n, precision) in the
+ * process on this plan's workspace (set PSN_TUNE=0 to keep the defaults).
+ * Synchronises `stream` before returning.  Idempotent.
  * Errors: PSN_EINVAL, PSN_ENOMEM, PSN_EDEVICE. */
 psn_status psn_kernel_build(psn_plan *p, void *stream);
 
@@ -120,6 +125,11 @@ psn_status psn_solve_batched(int count, psn_plan *const *plans,
  * in milliseconds to pass_ms[5].  For measurement only (it synchronises).
  * Errors: as psn_solve. */
 psn_status psn_solve_timed(psn_plan *p, const void *rho, void *u, void *stream, double *pass_ms);
+
+/* Override the tile schedule: candidate p24 (0..2) for the axis-1 passes and
+ * p3 (0..2) for the axis-0 pass.  Every candidate computes the same result.
+ * Errors: PSN_EINVAL. */
+psn_status psn_plan_set_schedule(psn_plan *p, int p24, int p3);
 
 /* Fill *info.  Errors: PSN_EINVAL. */
 psn_status psn_plan_query(const psn_plan *p, psn_plan_info *info);

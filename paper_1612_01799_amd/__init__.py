@@ -45,7 +45,8 @@ class PlanInfo(ctypes.Structure):
         ("terms", ctypes.c_int), ("eps_achieved", ctypes.c_double), ("C0", ctypes.c_double),
         ("C2", ctypes.c_double), ("built", ctypes.c_int), ("device_bytes", ctypes.c_size_t),
         ("algorithmic_bytes", ctypes.c_double), ("a", ctypes.c_double * 3), ("b", ctypes.c_double * 3),
-        ("h3", ctypes.c_double * 3), ("T3", ctypes.c_double * 3),
+        ("h3", ctypes.c_double * 3), ("T3", ctypes.c_double * 3), ("schedule", ctypes.c_int * 2),
+        ("tuned", ctypes.c_int),
     ]
 
 
@@ -75,6 +76,7 @@ def _load():
         "psn_plan_gs_table": (ctypes.c_int, [P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
                                              ctypes.c_int, ctypes.POINTER(ctypes.c_int)]),
         "psn_kernel_download": (ctypes.c_int, [P, ctypes.POINTER(ctypes.c_double)]),
+        "psn_plan_set_schedule": (ctypes.c_int, [P, ctypes.c_int, ctypes.c_int]),
         "psn_plan_destroy": (None, [P]),
         "psn_strerror": (ctypes.c_char_p, [ctypes.c_int]),
         "psn_last_error": (ctypes.c_char_p, []),
@@ -160,6 +162,10 @@ class Plan:
                                     _stream_handle(stream), ms.ctypes.data_as(ctypes.POINTER(ctypes.c_double))),
                "psn_solve_timed")
         return ms
+
+    def set_schedule(self, p24: int, p3: int) -> "Plan":
+        _check(_lib.psn_plan_set_schedule(self._h, int(p24), int(p3)), "psn_plan_set_schedule")
+        return self
 
     # -- introspection
     def info(self) -> dict:

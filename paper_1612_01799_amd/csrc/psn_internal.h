@@ -35,6 +35,9 @@ struct psn_plan {
     void* W1lo = nullptr; // SPLIT low parts
     void* W2lo = nullptr;
     size_t device_bytes = 0;
+    // schedule of the strided passes (candidate indices, see Sched)
+    int sched24 = 0, sched3 = 0;
+    bool tuned = false;
 };
 
 namespace psn_host {
@@ -55,6 +58,16 @@ struct Slot {
 // per pass per 32 slots).  With `ev` non-null, ev[0] is recorded before the
 // first pass and ev[i] after pass i (i = 1..5).
 hipError_t launch_group(const Slot* slots, int count, hipStream_t stream, hipEvent_t* ev = nullptr);
+hipError_t launch_group_f64(const Slot* slots, int count, hipStream_t stream, hipEvent_t* ev);
+hipError_t launch_group_f32(const Slot* slots, int count, hipStream_t stream, hipEvent_t* ev);
+hipError_t launch_group_split(const Slot* slots, int count, hipStream_t stream, hipEvent_t* ev);
+
+// Time the compiled tile candidates of the strided passes on the plan's own
+// workspace (synchronises `stream`) and return the fastest.
+hipError_t tune_f64(const psn_plan* p, hipStream_t stream, int* best24, int* best3);
+hipError_t tune_f32(const psn_plan* p, hipStream_t stream, int* best24, int* best3);
+hipError_t tune_split(const psn_plan* p, hipStream_t stream, int* best24, int* best3);
+constexpr int kScheduleCandidates = 3;
 
 // Kernel spectrum build on the device (FP64), written into p->K / p->Kb in
 // the plan's storage type, plus C0/C2 into the two doubles at d_c.

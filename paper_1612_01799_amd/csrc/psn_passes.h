@@ -27,6 +27,8 @@
 //   P4  axis 1, inverse           W2  -> W1   (M inputs, n outputs)
 //   P5  axis 2, complex -> real   W1  -> u
 // The 1/M^3 of the inverse transform is folded into K.
+#pragma once
+
 #include "psn_device.h"
 #include "psn_internal.h"
 
@@ -473,39 +475,154 @@ inline bool allow_lds(const void* fn, size_t bytes) {
     return hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, int(bytes)) == hipSuccess;
 }
 
-// Enqueue the six kernels of one solve for bt.count problems of size N.
+// ------------------------------------------------------------------ schedules
+// Tile shapes of the strided passes: B adjacent columns per workgroup, TT
+// threads per line.  Each pass has three compiled candidates; the autotuner
+// times them once per (n, precision) and keeps the fastest.  A candidate that
+// does not fit (LDS, threads, radix plan) is replaced by candidate 0.
+struct TileV {
+    int B, TT;
+};
+
+constexpr bool tile_ok(int N, TileV v, int cxbytes) {
+    return v.B >= 1 && v.TT >= 1 && N % v.B == 0 && N % v.TT == 0 && v.B * v.TT <= 1024 &&
+           (2 * v.B * N + ((2 * N + 15) & ~15)) * cxbytes <= kMaxLdsP3 && make_plan(N, N / v.TT).n > 0 &&
+           N / v.TT <= 20;
+}
+
+constexpr TileV pick_tile(int N, TileV v, TileV dflt, int cxbytes) { return tile_ok(N, v, cxbytes) ? v : dflt; }
+
 template <int N, int DT>
-hipError_t solve_n(const Batch<DT>& bt, hipStream_t s, hipEvent_t* ev) {
+struct Sched {
+    using C = Cfg<N, DT>;
+    static constexpr int e8 = elems_per_thread(N, 8), e16 = elems_per_thread(N, 4);
+    static constexpr TileV d24{C::BS, C::T24}, d3{C::BP3, C::T3};
+    static constexpr TileV v24[3] = {d24, pick_tile(N, {2 * C::BS, N / e8}, d24, C::CX),
+                                     pick_tile(N, {C::BS, N / e16}, d24, C::CX)};
+    static constexpr TileV v3[3] = {d3, pick_tile(N, {DT == DT_F32 ? C::BP3 / 2 : 2 * C::BP3, N / e8}, d3, C::CX),
+                                    pick_tile(N, {C::BP3, N / e16}, d3, C::CX)};
+    static_assert(tile_ok(N, d24, C::CX) && tile_ok(N, d3, C::CX), "default tiles must fit");
+};
+
+template <int N, int DT, int I>
+hipError_t launch_p2(const Batch<DT>& bt, hipStream_t s) {
+    constexpr TileV v = Sched<N, DT>::v24[I];
+    const size_t lds = (size_t(2) * v.B * N + TwLds<typename Cfg<N, DT>::Real>::slots(N)) * Cfg<N, DT>::CX;
+    static const bool ok = allow_lds(reinterpret_cast<const void*>(&p2_fwd<N, DT, v.B, v.TT>), lds);
+    if (!ok) return hipErrorInvalidConfiguration;
+    hipLaunchKernelGGL((p2_fwd<N, DT, v.B, v.TT>), dim3(xcd_grid(long(bt.count) * N * (N / v.B))), dim3(v.B * v.TT),
+                       lds, s, bt);
+    return hipSuccess;
+}
+
+template <int N, int DT, int I>
+hipError_t launch_p4(const Batch<DT>& bt, hipStream_t s) {
+    constexpr TileV v = Sched<N, DT>::v24[I];
+    const size_t lds = (size_t(2) * v.B * N + TwLds<typename Cfg<N, DT>::Real>::slots(N)) * Cfg<N, DT>::CX;
+    static const bool ok = allow_lds(reinterpret_cast<const void*>(&p4_inv<N, DT, v.B, v.TT>), lds);
+    if (!ok) return hipErrorInvalidConfiguration;
+    hipLaunchKernelGGL((p4_inv<N, DT, v.B, v.TT>), dim3(xcd_grid(long(bt.count) * N * (N / v.B))), dim3(v.B * v.TT),
+                       lds, s, bt);
+    return hipSuccess;
+}
+
+template <int N, int DT, int I>
+hipError_t launch_p3(const Batch<DT>& bt, hipStream_t s) {
+    constexpr TileV v = Sched<N, DT>::v3[I];
+    const size_t lds = (size_t(2) * v.B * N + TwLds<typename Cfg<N, DT>::Real>::slots(N)) * Cfg<N, DT>::CX;
+    static const bool ok = allow_lds(reinterpret_cast<const void*>(&p3_conv<N, DT, v.B, v.TT>), lds);
+    if (!ok) return hipErrorInvalidConfiguration;
+    hipLaunchKernelGGL((p3_conv<N, DT, v.B, v.TT>), dim3(xcd_grid(long(bt.count) * 2 * N * (N / v.B))),
+                       dim3(v.B * v.TT), lds, s, bt);
+    return hipSuccess;
+}
+
+template <int N, int DT>
+hipError_t launch_p24(const Batch<DT>& bt, hipStream_t s, int v, bool forward) {
+    switch (v) {
+        case 1: return forward ? launch_p2<N, DT, 1>(bt, s) : launch_p4<N, DT, 1>(bt, s);
+        case 2: return forward ? launch_p2<N, DT, 2>(bt, s) : launch_p4<N, DT, 2>(bt, s);
+        default: return forward ? launch_p2<N, DT, 0>(bt, s) : launch_p4<N, DT, 0>(bt, s);
+    }
+}
+
+template <int N, int DT>
+hipError_t launch_p3v(const Batch<DT>& bt, hipStream_t s, int v) {
+    switch (v) {
+        case 1: return launch_p3<N, DT, 1>(bt, s);
+        case 2: return launch_p3<N, DT, 2>(bt, s);
+        default: return launch_p3<N, DT, 0>(bt, s);
+    }
+}
+
+// Enqueue the six kernels of one solve for bt.count problems of size N with
+// schedule (v24 for P2/P4, v3 for P3).
+template <int N, int DT>
+hipError_t solve_n(const Batch<DT>& bt, hipStream_t s, hipEvent_t* ev, int v24, int v3) {
     using C = Cfg<N, DT>;
     constexpr size_t tws = TwLds<typename C::Real>::slots(N);
     const size_t lds_rows = (size_t(C::LC) * C::NP + tws) * C::CX;
-    const size_t lds_cols = (size_t(2) * C::BS * N + tws) * C::CX;
-    const size_t lds_p3 = (size_t(2) * C::BP3 * N + tws) * C::CX;
     const size_t lds_c0 = size_t(2) * N * C::CX;
-    static const bool lds_ok = allow_lds(reinterpret_cast<const void*>(&p2_fwd<N, DT, C::BS, C::T24>), lds_cols) &&
-                               allow_lds(reinterpret_cast<const void*>(&p4_inv<N, DT, C::BS, C::T24>), lds_cols) &&
-                               allow_lds(reinterpret_cast<const void*>(&p3_conv<N, DT, C::BP3, C::T3>), lds_p3);
-    if (!lds_ok) return hipErrorInvalidConfiguration;
     const long cnt = bt.count;
     auto mark = [&](int i) {
         if (ev) (void)hipEventRecord(ev[i], s);
     };
+    hipError_t e;
     mark(0);
     hipLaunchKernelGGL((p1_r2c<N, DT>), dim3(xcd_grid(cnt * N * N / C::LC)), dim3(C::LC * C::T), lds_rows, s, bt);
     mark(1);
-    hipLaunchKernelGGL((p2_fwd<N, DT, C::BS, C::T24>), dim3(xcd_grid(cnt * N * (N / C::BS))), dim3(C::BS * C::T24),
-                       lds_cols, s, bt);
+    if ((e = launch_p24<N, DT>(bt, s, v24, true)) != hipSuccess) return e;
     mark(2);
-    hipLaunchKernelGGL((p3_conv<N, DT, C::BP3, C::T3>), dim3(xcd_grid(cnt * 2 * N * (N / C::BP3))),
-                       dim3(C::BP3 * C::T3), lds_p3, s, bt);
+    if ((e = launch_p3v<N, DT>(bt, s, v3)) != hipSuccess) return e;
     hipLaunchKernelGGL((p3_col0<N, DT>), dim3(cnt * N), dim3(2 * C::T), lds_c0, s, bt);
     mark(3);
-    hipLaunchKernelGGL((p4_inv<N, DT, C::BS, C::T24>), dim3(xcd_grid(cnt * N * (N / C::BS))), dim3(C::BS * C::T24),
-                       lds_cols, s, bt);
+    if ((e = launch_p24<N, DT>(bt, s, v24, false)) != hipSuccess) return e;
     mark(4);
     hipLaunchKernelGGL((p5_c2r<N, DT>), dim3(xcd_grid(cnt * N * N / C::LC)), dim3(C::LC * C::T), lds_rows, s, bt);
     mark(5);
     return hipGetLastError();
+}
+
+// Time the candidates of the strided passes on one problem's workspace
+// (contents are irrelevant to the timing) and return the fastest indices.
+template <int N, int DT>
+hipError_t tune_n(const Batch<DT>& bt, hipStream_t s, int* best24, int* best3) {
+    hipEvent_t a = nullptr, b = nullptr;
+    hipError_t e = hipEventCreate(&a);
+    if (e == hipSuccess) e = hipEventCreate(&b);
+    auto timed = [&](auto&& launch, float* ms) -> hipError_t {
+        float best = 1e30f;
+        for (int r = 0; r < 4; ++r) {
+            hipError_t le = hipEventRecord(a, s);
+            if (le == hipSuccess) le = launch();
+            if (le == hipSuccess) le = hipEventRecord(b, s);
+            if (le == hipSuccess) le = hipEventSynchronize(b);
+            float t = 0.f;
+            if (le == hipSuccess) le = hipEventElapsedTime(&t, a, b);
+            if (le != hipSuccess) return le;
+            if (r > 0 && t < best) best = t;  // first run warms up
+        }
+        *ms = best;
+        return hipSuccess;
+    };
+    float t24[3] = {1e30f, 1e30f, 1e30f}, t3[3] = {1e30f, 1e30f, 1e30f};
+    for (int v = 0; v < 3 && e == hipSuccess; ++v) {
+        e = timed([&] {
+                hipError_t x = launch_p24<N, DT>(bt, s, v, true);
+                return x == hipSuccess ? launch_p24<N, DT>(bt, s, v, false) : x;
+            }, &t24[v]);
+        if (e == hipSuccess) e = timed([&] { return launch_p3v<N, DT>(bt, s, v); }, &t3[v]);
+    }
+    if (a) (void)hipEventDestroy(a);
+    if (b) (void)hipEventDestroy(b);
+    if (e != hipSuccess) return e;
+    *best24 = 0;
+    *best3 = 0;
+    for (int v = 1; v < 3; ++v) {
+        if (t24[v] < 0.97f * t24[*best24]) *best24 = v;
+        if (t3[v] < 0.97f * t3[*best3]) *best3 = v;
+    }
+    return hipSuccess;
 }
 
 template <int DT>
@@ -529,9 +646,10 @@ Prob<DT> prob_of(const psn_host::Slot& sl) {
     return pr;
 }
 
-// Slots [first, first + count) share n and precision.
+// Slots [0, count) share n and precision; the first slot's plan gives the schedule.
 template <int DT>
 hipError_t solve_group(const psn_host::Slot* slots, int count, hipStream_t s, hipEvent_t* ev) {
+    const int v24 = slots[0].plan->sched24, v3 = slots[0].plan->sched3;
     for (int base = 0; base < count; base += kMaxBatch) {
         Batch<DT> bt{};
         bt.count = count - base < kMaxBatch ? count - base : kMaxBatch;
@@ -539,7 +657,7 @@ hipError_t solve_group(const psn_host::Slot* slots, int count, hipStream_t s, hi
         hipError_t e = hipErrorInvalidValue;
         switch (slots[0].plan->n) {
 #define PSN_CASE(NN) \
-    case NN: e = solve_n<NN, DT>(bt, s, ev); break;
+    case NN: e = solve_n<NN, DT>(bt, s, ev, v24, v3); break;
             PSN_FOR_EACH_SIZE(PSN_CASE)
 #undef PSN_CASE
             default: break;
@@ -549,28 +667,29 @@ hipError_t solve_group(const psn_host::Slot* slots, int count, hipStream_t s, hi
     return hipSuccess;
 }
 
-}  // namespace psn
-
-namespace psn_host {
-
-hipError_t launch_group(const Slot* slots, int count, hipStream_t stream, hipEvent_t* ev) {
-    if (count <= 0) return hipSuccess;
-    switch (slots[0].plan->dtype) {
-        case PSN_F64: return psn::solve_group<psn::DT_F64>(slots, count, stream, ev);
-        case PSN_F32: return psn::solve_group<psn::DT_F32>(slots, count, stream, ev);
-        case PSN_SPLIT: return psn::solve_group<psn::DT_SPLIT>(slots, count, stream, ev);
-    }
-    return hipErrorInvalidValue;
-}
-
-bool size_compiled(int n) {
-    switch (n) {
+template <int DT>
+hipError_t tune_plan(const psn_plan* p, hipStream_t s, int* best24, int* best3) {
+    Batch<DT> bt{};
+    bt.count = 1;
+    bt.p[0] = prob_of<DT>(psn_host::Slot{p, nullptr, nullptr, p->W1, p->W2, p->W1lo, p->W2lo});
+    switch (p->n) {
 #define PSN_CASE(NN) \
-    case NN: return true;
+    case NN: return tune_n<NN, DT>(bt, s, best24, best3);
         PSN_FOR_EACH_SIZE(PSN_CASE)
 #undef PSN_CASE
-        default: return false;
+        default: return hipErrorInvalidValue;
     }
 }
 
-}  // namespace psn_host
+}  // namespace psn
+
+// Defines the per-precision entry points of one compilation unit.
+#define PSN_DEFINE_PRECISION(DTV, SUFFIX)                                                                       \
+    namespace psn_host {                                                                                        \
+    hipError_t launch_group_##SUFFIX(const Slot* slots, int count, hipStream_t stream, hipEvent_t* ev) {       \
+        return psn::solve_group<DTV>(slots, count, stream, ev);                                                 \
+    }                                                                                                           \
+    hipError_t tune_##SUFFIX(const psn_plan* p, hipStream_t stream, int* best24, int* best3) {                \
+        return psn::tune_plan<DTV>(p, stream, best24, best3);                                                   \
+    }                                                                                                           \
+    }

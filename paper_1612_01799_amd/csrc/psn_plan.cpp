@@ -141,6 +141,34 @@ void free_device(psn_plan* p) {
 
 bool is_real_dtype(int d) { return d == PSN_F64 || d == PSN_F32 || d == PSN_SPLIT; }
 
+// Autotuned schedules, once per (n, precision) and process.  PSN_TUNE=0 keeps
+// the default tiles.
+std::mutex g_tune_mutex;
+std::map<std::pair<int, int>, std::pair<int, int>> g_tuned;
+
+psn_status tune_schedule(psn_plan* p, hipStream_t s) {
+    const char* env = std::getenv("PSN_TUNE");
+    if (env && env[0] == '0') return PSN_OK;
+    std::lock_guard<std::mutex> lock(g_tune_mutex);
+    const auto key = std::make_pair(p->n, int(p->dtype));
+    auto it = g_tuned.find(key);
+    if (it == g_tuned.end()) {
+        int b24 = 0, b3 = 0;
+        hipError_t e = hipErrorInvalidValue;
+        switch (p->dtype) {
+            case PSN_F64: e = psn_host::tune_f64(p, s, &b24, &b3); break;
+            case PSN_F32: e = psn_host::tune_f32(p, s, &b24, &b3); break;
+            case PSN_SPLIT: e = psn_host::tune_split(p, s, &b24, &b3); break;
+        }
+        if (!hip_ok(e, "schedule tuning")) return PSN_EDEVICE;
+        it = g_tuned.emplace(key, std::make_pair(b24, b3)).first;
+    }
+    p->sched24 = it->second.first;
+    p->sched3 = it->second.second;
+    p->tuned = true;
+    return PSN_OK;
+}
+
 size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
 
 // workspace bytes of one solve: W1 (n^3 complex), W2 (2 n^3 complex), and the
@@ -192,6 +220,26 @@ std::map<int, BatchCache> g_batch;
 }  // namespace
 
 namespace psn_host {
+
+hipError_t launch_group(const Slot* slots, int count, hipStream_t stream, hipEvent_t* ev) {
+    if (count <= 0) return hipSuccess;
+    switch (slots[0].plan->dtype) {
+        case PSN_F64: return launch_group_f64(slots, count, stream, ev);
+        case PSN_F32: return launch_group_f32(slots, count, stream, ev);
+        case PSN_SPLIT: return launch_group_split(slots, count, stream, ev);
+    }
+    return hipErrorInvalidValue;
+}
+
+bool size_compiled(int n) {
+    switch (n) {
+#define PSN_CASE(NN) \
+    case NN: return true;
+        PSN_FOR_EACH_SIZE(PSN_CASE)
+#undef PSN_CASE
+        default: return false;
+    }
+}
 
 size_t elem_bytes(psn_dtype dt) { return dt == PSN_F64 ? 16 : 8; }
 size_t kernel_elem_bytes(psn_dtype dt) { return dt == PSN_F32 ? 4 : 8; }
@@ -324,7 +372,7 @@ psn_status psn_kernel_build(psn_plan* p, void* stream) {
     p->C0 = cc[0];
     p->C2 = cc[1];
     p->built = true;
-    return PSN_OK;
+    return tune_schedule(p, s);
 }
 
 psn_status psn_solve(psn_plan* p, const void* rho, void* u, void* stream) {
@@ -455,6 +503,9 @@ psn_status psn_plan_query(const psn_plan* p, psn_plan_info* info) {
     info->h = p->h[0];
     info->T = p->T[0];
     info->period = p->period[0];
+    info->schedule[0] = p->sched24;
+    info->schedule[1] = p->sched3;
+    info->tuned = p->tuned ? 1 : 0;
     for (int q = 0; q < 3; ++q) {
         info->a[q] = p->a[q];
         info->b[q] = p->b[q];
@@ -477,6 +528,15 @@ psn_status psn_plan_query(const psn_plan* p, psn_plan_info* info) {
     const double bs = p->dtype == PSN_F32 ? 4 : (p->dtype == PSN_F64 ? 8 : 6);
     const double bk = p->dtype == PSN_F32 ? 4 : 8;
     info->algorithmic_bytes = 2 * bio * n3 + 24 * bs * n3 + bk * np1 * np1 * np1;
+    return PSN_OK;
+}
+
+psn_status psn_plan_set_schedule(psn_plan* p, int p24, int p3) {
+    if (!p || p24 < 0 || p24 >= psn_host::kScheduleCandidates || p3 < 0 || p3 >= psn_host::kScheduleCandidates)
+        return PSN_EINVAL;
+    p->sched24 = p24;
+    p->sched3 = p3;
+    p->tuned = false;
     return PSN_OK;
 }
 

@@ -135,6 +135,16 @@ def test_algorithmic_bytes():
         assert info["algorithmic_bytes"] == 2 * bio * n ** 3 + 24 * bs * n ** 3 + bk * (n + 1) ** 3
 
 
+def test_schedule_override_validation():
+    p = psn.Plan(32, 1.0, 1e-12, "f32")
+    p.set_schedule(2, 1)
+    assert p.info()["schedule"] == (2, 1) and p.info()["tuned"] == 0
+    for bad in [(-1, 0), (3, 0), (0, 3)]:
+        with pytest.raises(psn.PsnError) as e:
+            p.set_schedule(*bad)
+        assert e.value.status == -1
+
+
 def test_strerror():
     for st in range(-6, 1):
         assert psn._lib.psn_strerror(st)

@@ -281,3 +281,34 @@ def test_batched_after_plan_destroyed():
         torch.cuda.synchronize()
         assert max_rel(out.cpu().numpy(), O.solve(rho_np, oracle_symbol(n, L))) <= TOL["f64"]
         plan.close()
+
+
+@pytest.mark.parametrize("n", [24, 48, 96, 128, 160, 256])
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+def test_every_schedule_candidate(n, dtype):
+    """All compiled tile candidates of the strided passes give the oracle's result."""
+    torch = torch_cuda()
+    L = 2.0 + n / 64.0
+    rho = _mix(n, L, 300 + n)
+    ref = O.solve(rho, oracle_symbol(n, L))
+    plan = psn.Plan(n, L, 1e-12, dtype).build()
+    info = plan.info()
+    assert info["tuned"] == 1 and all(0 <= v < 3 for v in info["schedule"])
+    for s in [(0, 0), (1, 1), (2, 2), (1, 2), (2, 0)]:
+        plan.set_schedule(*s)
+        u = gpu_solve(psn, torch, n, L, dtype, rho, plan=plan)
+        assert max_rel(u, ref) <= TOL[dtype], s
+
+
+def test_every_schedule_candidate_n512():
+    torch = torch_cuda()
+    mix = W.config_n512()
+    if "ref" not in _cache512:
+        rho = W.mixture_density(mix)
+        _cache512["rho"] = rho
+        _cache512["ref"] = O.solve(rho, O.half_spectrum(O.kernel_spectrum(mix.box, 1e-12)))
+    plan = psn.Plan(512, 12.0, 1e-12, "f32").build()
+    for s in [(0, 0), (1, 1), (2, 2)]:
+        plan.set_schedule(*s)
+        u = gpu_solve(psn, torch, 512, 12.0, "f32", _cache512["rho"], plan=plan)
+        assert max_rel(u, _cache512["ref"]) <= TOL["f32"], s
