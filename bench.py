@@ -147,6 +147,50 @@ def bench_batched(psn, torch, np, steps, warmup, with_oracle):
     return out
 
 
+def bench_size(psn, torch, np, n, steps, warmup, with_oracle):
+    """F32 and F64 solve times of one more benchmark size (the metric names 256^3 and 512^3)."""
+    import workloads as W
+    mix, desc = workload(n)
+    L = mix.box.b[0]
+    rho_np = W.mixture_density(mix)
+    rho64 = torch.from_numpy(rho_np).to("cuda")
+    out = {"workload": desc, "n": n}
+    us = {}
+    for dt in ("f32", "f64"):
+        p, r, u, ms = time_path(psn, torch, n, L, dt, rho64, steps, warmup)
+        out[f"{dt}_ms"] = ms
+        out[f"{dt}_value"] = n ** 3 / (ms * 1e-3)
+        out[f"{dt}_hbm_frac"] = p.info()["algorithmic_bytes"] / (ms * 1e-3) / HBM_PEAK
+        us[dt] = u.double().cpu().numpy()
+        del p, r, u
+    out["speedup_vs_f64"] = out["f64_ms"] / out["f32_ms"]
+    out["max_rel_err_vs_oracle"] = None
+    if with_oracle:
+        import oracle as O
+        ref = O.solve(rho_np, O.half_spectrum(O.kernel_spectrum(mix.box, 1e-12)), workers=min(16, os.cpu_count() or 1))
+        out["max_rel_err_vs_oracle"] = {k: float(np.max(np.abs(v - ref)) / np.max(np.abs(ref))) for k, v in us.items()}
+    return out
+
+
+def radix16_probe():
+    """Radix-16 DFTs per second: VALU butterflies vs FP32 MFMA (built by build.py)."""
+    import subprocess
+    exe = os.path.join(ROOT, "paper_1612_01799_amd", "dft16_valu_vs_mfma")
+    if not os.path.exists(exe):
+        return None
+    r = subprocess.run([exe], capture_output=True, text=True, timeout=120)
+    out = {}
+    for tok in r.stdout.split():
+        k, _, v = tok.partition("=")
+        try:
+            out[k] = float(v)
+        except ValueError:
+            out[k] = v
+    if r.returncode == 0 and "valu_dft16_per_s" in out:
+        out["valu_over_mfma"] = out["valu_dft16_per_s"] / out["mfma_dft16_per_s"]
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -156,6 +200,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-compare", action="store_true", help="skip the FP64 and split paths")
     ap.add_argument("--no-batched", action="store_true", help="skip the mixed-size batched workload")
+    ap.add_argument("--extra-n", type=int, default=256, help="second benchmark size (0 = none)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one 1 GiB device-to-device tensor copy (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -244,12 +289,23 @@ def main():
             errs[k] = float(np.max(np.abs(v - uref)) / scale)
         log("oracle errors: " + ", ".join(f"{k}={v:.2e}" for k, v in errs.items()))
 
+    second = None
+    if args.extra_n and args.extra_n != n:
+        log(f"timing n={args.extra_n}")
+        second = bench_size(psn, torch, np, args.extra_n, args.steps, args.warmup, not args.no_cpu)
+        log(f"n={args.extra_n}: f32 {second['f32_ms']:.3f} ms, f64 {second['f64_ms']:.3f} ms, "
+            f"err {second['max_rel_err_vs_oracle']}")
+
     batched = None
     if not args.no_batched:
         log("timing the batched mixed-size workload")
         batched = bench_batched(psn, torch, np, max(3, args.steps // 2), args.warmup, not args.no_cpu)
         log(f"batched: {batched['ms_per_batch']:.3f} ms/batch ({batched['ms_one_by_one']:.3f} ms one by one), "
             f"err {batched['max_rel_err_vs_oracle']}")
+
+    log("radix-16 DFT: VALU butterflies vs FP32 MFMA")
+    r16 = radix16_probe()
+    log(f"radix-16: {r16}")
 
     value = n ** 3 / (ms32 * 1e-3)
     line = {
@@ -279,7 +335,9 @@ def main():
         "split_path": extra.get("split"),
         "speedup_vs_f64": (extra["f64"]["ms_per_step"] / ms32) if "f64" in extra else None,
         "max_rel_err_vs_oracle": errs or None,
+        f"n{args.extra_n}": second,
         "batched": batched,
+        "radix16_valu_vs_mfma": r16,
     }
     print(json.dumps(line), flush=True)
 

@@ -62,6 +62,13 @@ def build_library(verbose: bool = False, jobs: int = 5) -> str:
     if r.returncode != 0:
         raise RuntimeError(f"link failed\n{r.stdout}\n{r.stderr}")
     os.replace(tmp, LIB)
+    # radix-16 microbenchmark (VALU butterflies vs MFMA), run by bench.py
+    exe = os.path.join(HERE, "dft16_valu_vs_mfma")
+    cmd = [hipcc, *FLAGS, "-x", "hip", os.path.join(CSRC, "microbench", "dft16_valu_vs_mfma.hip"), "-o", exe + ".tmp"]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"compile failed: dft16_valu_vs_mfma\n{r.stdout}\n{r.stderr}")
+    os.replace(exe + ".tmp", exe)
     return LIB
 
 
