@@ -42,6 +42,18 @@ struct psn_plan {
 
 namespace psn_host {
 
+// k1 block of the W2 layout: the largest power of two <= sqrt(2n) dividing 2n
+constexpr int w2_k1_block(int n) {
+    int kb = 1;
+    while ((2 * kb) * (2 * kb) <= 2 * n && (2 * n) % (2 * kb) == 0) kb *= 2;
+    return kb;
+}
+constexpr size_t kW2BlockPad = 512;  // elements between k1 blocks of W2
+// complex elements of W2 (n * 2n * n plus the block pads)
+constexpr size_t w2_elems(int n) {
+    return size_t(2) * n * n * n + size_t(2 * n / w2_k1_block(n)) * kW2BlockPad;
+}
+
 // One problem of a solve: its plan (kernel spectrum, twiddles), its input and
 // output, and the workspace it runs in (the plan's own, or a batch arena's).
 struct Slot {

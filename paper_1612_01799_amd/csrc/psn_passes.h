@@ -4,10 +4,9 @@
 // Layout (C order, last index contiguous), M = 2n:
 //   rho, u : [i0][i1][i2]            n^3 reals
 //   W1     : [i0][i1][k2]            n^3 complex, k2 = 0..n-1
-//   W2     : [k1/KB][i0][k1%KB][k2]  n * M * n complex, blocked over k1 so that
-//            both the axis-1 passes (fixed i0, all k1) and the axis-0 pass
-//            (fixed k1, all i0) touch about sqrt(M) distinct 2 MB pages
-//            per line instead of M or n
+//   W2     : n * M * n complex, blocked over k1 and tiled over k2 (W2Index)
+//            so that both the axis-1 passes (fixed i0, all k1) and the axis-0
+//            pass (fixed k1, all i0) read and write long contiguous runs
 //   K      : [k1~][k0~][k2]          (n+1)^2 * n reals, folded k~ = min(k, M-k)
 //   Kb     : [k1~][k0~]              (n+1)^2 reals
 // The real-to-complex transform along axis 2 gives n+1 frequencies; the two
@@ -49,6 +48,15 @@ constexpr int pick_cols_p3(int N, int bmax, int cxbytes, int T) {
     return 1;
 }
 
+// largest P3 tile width <= bmax that fits and divides the W2 layout tile
+constexpr int pick_cols_p3_div(int N, int bmax, int cxbytes, int T, int layout_tile) {
+    for (int b = bmax; b >= 1; --b)
+        if (N % b == 0 && layout_tile % b == 0 && (2 * b * N + ((2 * N + 15) & ~15)) * cxbytes <= kMaxLdsP3 &&
+            b * T <= 1024)
+            return b;
+    return 1;
+}
+
 constexpr int rows_padded(int N) { return N + (N >> 4) + 1; }
 
 constexpr int pick_lines(int N, int T, int cxbytes) {
@@ -58,22 +66,31 @@ constexpr int pick_lines(int N, int T, int cxbytes) {
     return l;
 }
 
-// k1 block of the W2 layout: the largest power of two <= sqrt(2N) dividing 2N
-constexpr int k1_block(int N) {
-    int kb = 1;
-    while ((2 * kb) * (2 * kb) <= 2 * N && (2 * N) % (2 * kb) == 0) kb *= 2;
-    return kb;
-}
-
-template <int N>
+// W2 layout, tile-major: element (i0, k1, k2) lives at
+//   slot / KB * blk + (i0 * (N / BL) + k2 / BL) * (KB * BL) + (slot % KB) * BL + k2 % BL
+// with slot(k1) putting rows k1 and M-k1 next to each other (rows 0 and n
+// form pair 0) and blk = N * N * KB plus a small pad, so that the k1 blocks of
+// one tile, otherwise a power of two apart, do not share cache sets.  So the axis-1 passes (one i0, one tile of BL columns, all k1)
+// write and read runs of KB * BL contiguous elements, and the two workgroups
+// of the axis-0 pass that share a kernel row (k1 and M-k1) read the two halves
+// of the same 128-byte lines.  BL is the column tile of the axis-1 passes.
+template <int N, int BL>
 struct W2Index {
-    static constexpr int KB = k1_block(N);
-    // element (i0, k1, k2)
+    static constexpr int KB = psn_host::w2_k1_block(N);
+    static constexpr size_t blk = size_t(N) * N * KB + psn_host::kW2BlockPad;  // stride of k1 blocks
+    static_assert(N % BL == 0 && (2 * N) % KB == 0, "");
+    static __device__ __forceinline__ int slot(int k1) {
+        if (k1 == 0) return 0;
+        if (k1 == N) return 1;
+        return k1 < N ? 2 * k1 : 2 * (2 * N - k1) + 1;
+    }
     static __device__ __forceinline__ size_t at(int i0, int k1, int k2) {
-        return (size_t(k1 / KB) * N + i0) * (size_t(KB) * N) + size_t(k1 % KB) * N + k2;
+        const int sl = slot(k1);
+        return size_t(sl / KB) * blk + (size_t(i0) * (N / BL) + k2 / BL) * size_t(KB * BL) + size_t(sl % KB) * BL +
+               k2 % BL;
     }
     // stride between consecutive i0 at fixed (k1, k2)
-    static constexpr size_t s0 = size_t(KB) * N;
+    static constexpr size_t s0 = size_t(N) * KB;
 };
 
 template <int N, int DT>
@@ -88,7 +105,8 @@ struct Cfg {
     static constexpr int T24 = N / elems_per_thread(N, 8);                     // P2, P4 team (two chains)
     static constexpr int BS = pick_cols_p3(N, 8, CX, T24);                     // P2, P4 columns
     static constexpr int T3 = N / elems_per_thread(N, 8);                      // P3 team (two chains)
-    static constexpr int BP3 = pick_cols_p3(N, DT == DT_F32 ? 8 : 4, CX, T3);  // P3 columns
+    static constexpr int BP3 = pick_cols_p3_div(N, DT == DT_F32 ? 8 : 4, CX, T3, BS);  // P3 columns (divide BS)
+    static_assert(BS % BP3 == 0, "P3 tile must lie inside the W2 layout tile");
     static constexpr int LC = pick_lines(N, T, CX);                            // P1, P5 lines
     static constexpr int NP = rows_padded(N);
 };
@@ -187,7 +205,8 @@ p2_fwd(const Batch<DT> bt) {
     using C = Cfg<N, DT>;
     using Real = typename C::Real;
     using F = TeamFFT<N, TT, Real, -1, false>;
-    using WI = W2Index<N>;
+    using WI = W2Index<N, Cfg<N, DT>::BS>;
+    static_assert(B == Cfg<N, DT>::BS, "the axis-1 tile is the W2 layout tile");
     constexpr int E = F::E;
     constexpr int tiles = N / B;
     constexpr int units = N * tiles;  // per problem
@@ -247,7 +266,9 @@ p3_conv(const Batch<DT> bt) {
     constexpr int E = Ff::E;
     constexpr int tiles = N / B;
     constexpr int units = 2 * N * tiles;   // per problem: rows k1 and M-k1 of each (pair, tile)
-    constexpr size_t s0 = W2Index<N>::s0;  // stride of i0 in W2
+    using WI = W2Index<N, Cfg<N, DT>::BS>;
+    static_assert(Cfg<N, DT>::BS % B == 0, "the axis-0 tile lies inside a W2 layout tile");
+    constexpr size_t s0 = WI::s0;  // stride of i0 in W2
     extern __shared__ __align__(16) unsigned char smem[];
     cx<Real>* sb = reinterpret_cast<cx<Real>*>(smem);
     cx<Real>* stw = sb + 2 * B * N;
@@ -265,7 +286,7 @@ p3_conv(const Batch<DT> bt) {
     const int kt1 = k1 <= N ? k1 : 2 * N - k1;
     const int c = threadIdx.x % B, t = threadIdx.x / B;
     const int k2 = tile * B + c;
-    const size_t base = W2Index<N>::at(0, k1, k2);
+    const size_t base = WI::at(0, k1, k2);
     const typename C::Kt* Krow = K + size_t(kt1) * (N + 1) * N + k2;
 
     cx<Real> x[E], w[E];
@@ -319,7 +340,8 @@ p3_col0(const Batch<DT> bt) {
     using Real = typename C::Real;
     using Ff = TeamFFT<N, C::T, Real, -1, false>;
     using Fi = TeamFFT<N, C::T, Real, +1, true>;
-    constexpr size_t s0 = W2Index<N>::s0;
+    using WI = W2Index<N, Cfg<N, DT>::BS>;
+    constexpr size_t s0 = WI::s0;
     extern __shared__ __align__(16) unsigned char smem[];
     cx<Real>* sb = reinterpret_cast<cx<Real>*>(smem);
 
@@ -335,7 +357,7 @@ p3_col0(const Batch<DT> bt) {
     const int k1 = set == 0 ? q : (q == 0 ? N : 2 * N - q);
     const int kt1 = (q == 0) ? (set ? N : 0) : q;
     const int partner = (q == 0) ? set : 1 - set;
-    const size_t base = W2Index<N>::at(0, k1, 0);
+    const size_t base = WI::at(0, k1, 0);
     const typename C::Kt* Krow = K + size_t(kt1) * (N + 1) * N;
     const typename C::Kt* Kbr = Kb + size_t(kt1) * (N + 1);
 
@@ -382,7 +404,8 @@ p4_inv(const Batch<DT> bt) {
     using C = Cfg<N, DT>;
     using Real = typename C::Real;
     using F = TeamFFT<N, TT, Real, +1, false>;
-    using WI = W2Index<N>;
+    using WI = W2Index<N, Cfg<N, DT>::BS>;
+    static_assert(B == Cfg<N, DT>::BS, "the axis-1 tile is the W2 layout tile");
     constexpr int E = F::E;
     constexpr int tiles = N / B;
     constexpr int units = N * tiles;  // per problem
@@ -491,16 +514,20 @@ constexpr bool tile_ok(int N, TileV v, int cxbytes) {
 }
 
 constexpr TileV pick_tile(int N, TileV v, TileV dflt, int cxbytes) { return tile_ok(N, v, cxbytes) ? v : dflt; }
+constexpr TileV pick_tile3(int N, TileV v, TileV dflt, int cxbytes, int layout_tile) {
+    return (tile_ok(N, v, cxbytes) && layout_tile % v.B == 0) ? v : dflt;
+}
 
 template <int N, int DT>
 struct Sched {
     using C = Cfg<N, DT>;
     static constexpr int e8 = elems_per_thread(N, 8), e16 = elems_per_thread(N, 4);
     static constexpr TileV d24{C::BS, C::T24}, d3{C::BP3, C::T3};
-    static constexpr TileV v24[3] = {d24, pick_tile(N, {2 * C::BS, N / e8}, d24, C::CX),
-                                     pick_tile(N, {C::BS, N / e16}, d24, C::CX)};
-    static constexpr TileV v3[3] = {d3, pick_tile(N, {DT == DT_F32 ? C::BP3 / 2 : 2 * C::BP3, N / e8}, d3, C::CX),
-                                    pick_tile(N, {C::BP3, N / e16}, d3, C::CX)};
+    // P2/P4 keep the W2 layout tile (B = BS); P3 tiles must divide it
+    static constexpr TileV v24[3] = {d24, pick_tile(N, {C::BS, N / e16}, d24, C::CX), d24};
+    static constexpr TileV v3[3] = {
+        d3, pick_tile3(N, {C::BP3 / 2 >= 1 ? C::BP3 / 2 : 1, N / e8}, d3, C::CX, C::BS),
+        pick_tile3(N, {C::BP3, N / e16}, d3, C::CX, C::BS)};
     static_assert(tile_ok(N, d24, C::CX) && tile_ok(N, d3, C::CX), "default tiles must fit");
 };
 

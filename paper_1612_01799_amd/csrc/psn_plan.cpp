@@ -176,8 +176,9 @@ size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
 size_t slot_bytes(const psn_plan* p) {
     const size_t n3 = size_t(p->n) * p->n * p->n;
     const size_t wb = p->dtype == PSN_SPLIT ? 8 : psn_host::elem_bytes(p->dtype);
-    size_t b = align256(n3 * wb) + align256(2 * n3 * wb);
-    if (p->dtype == PSN_SPLIT) b += align256(n3 * 4) + align256(2 * n3 * 4);
+    const size_t w2 = psn_host::w2_elems(p->n);
+    size_t b = align256(n3 * wb) + align256(w2 * wb);
+    if (p->dtype == PSN_SPLIT) b += align256(n3 * 4) + align256(w2 * 4);
     return b;
 }
 
@@ -192,11 +193,11 @@ psn_host::Slot arena_slot(const psn_plan* p, const void* rho, void* u, char* bas
     sl.W1 = base;
     base += align256(n3 * wb);
     sl.W2 = base;
-    base += align256(2 * n3 * wb);
+    base += align256(psn_host::w2_elems(p->n) * wb);
     if (p->dtype == PSN_SPLIT) {
         sl.W1lo = base;
         base += align256(n3 * 4);
-        sl.W2lo = base;
+        sl.W2lo = base;  // sized by w2_elems as well
     }
     return sl;
 }
@@ -314,12 +315,14 @@ psn_status psn_kernel_build(psn_plan* p, void* stream) {
     const size_t wb = p->dtype == PSN_SPLIT ? 8 : psn_host::elem_bytes(p->dtype);
     if ((st = dev_alloc(&p->K, (n + 1) * (n + 1) * n * kb, &tot)) ||
         (st = dev_alloc(&p->Kb, (n + 1) * (n + 1) * kb, &tot)) || (st = dev_alloc(&p->tw, M * cxb, &tot)) ||
-        (st = dev_alloc(&p->W1, n * n * n * wb, &tot)) || (st = dev_alloc(&p->W2, n * M * n * wb, &tot))) {
+        (st = dev_alloc(&p->W1, n * n * n * wb, &tot)) ||
+        (st = dev_alloc(&p->W2, psn_host::w2_elems(p->n) * wb, &tot))) {
         free_device(p);
         return st;
     }
     if (p->dtype == PSN_SPLIT) {
-        if ((st = dev_alloc(&p->W1lo, n * n * n * 4, &tot)) || (st = dev_alloc(&p->W2lo, n * M * n * 4, &tot))) {
+        if ((st = dev_alloc(&p->W1lo, n * n * n * 4, &tot)) ||
+            (st = dev_alloc(&p->W2lo, psn_host::w2_elems(p->n) * 4, &tot))) {
             free_device(p);
             return st;
         }
