@@ -417,17 +417,36 @@ __device__ __forceinline__ float bf16_to_f32(uint32_t b) { return __uint_as_floa
 template <int DT>
 struct Work;
 
+// Global-memory load and store.  The workspace pointers reach a kernel through
+// a table in its arguments, from which the compiler cannot tell their address
+// space; a flat access would also count against the LDS wait counter and so
+// tie the wait for an LDS exchange to outstanding HBM traffic.
+#define PSN_GLOBAL __attribute__((address_space(1)))
+template <class R>
+using vec2 = R __attribute__((ext_vector_type(2)));
+template <class R>
+__device__ __forceinline__ cx<R> gld(const cx<R>* p) {
+    const vec2<R> v = *(const PSN_GLOBAL vec2<R>*)(p);
+    return {v.x, v.y};
+}
+template <class R>
+__device__ __forceinline__ void gst(cx<R>* p, cx<R> v) {
+    *(PSN_GLOBAL vec2<R>*)(p) = vec2<R>{v.x, v.y};
+}
+__device__ __forceinline__ uint32_t gld(const uint32_t* p) { return *(const PSN_GLOBAL uint32_t*)(p); }
+__device__ __forceinline__ void gst(uint32_t* p, uint32_t v) { *(PSN_GLOBAL uint32_t*)(p) = v; }
+
 template <>
 struct Work<DT_F32> {
     cx<float>* p;
-    __device__ __forceinline__ cx<float> ld(size_t i) const { return p[i]; }
-    __device__ __forceinline__ void st(size_t i, cx<float> v) const { p[i] = v; }
+    __device__ __forceinline__ cx<float> ld(size_t i) const { return gld(p + i); }
+    __device__ __forceinline__ void st(size_t i, cx<float> v) const { gst(p + i, v); }
 };
 template <>
 struct Work<DT_F64> {
     cx<double>* p;
-    __device__ __forceinline__ cx<double> ld(size_t i) const { return p[i]; }
-    __device__ __forceinline__ void st(size_t i, cx<double> v) const { p[i] = v; }
+    __device__ __forceinline__ cx<double> ld(size_t i) const { return gld(p + i); }
+    __device__ __forceinline__ void st(size_t i, cx<double> v) const { gst(p + i, v); }
 };
 // FP32 high part + bfloat16 low part (two per 32-bit word): 6 bytes per real.
 template <>
@@ -435,15 +454,15 @@ struct Work<DT_SPLIT> {
     cx<float>* hi;
     uint32_t* lo;
     __device__ __forceinline__ cx<double> ld(size_t i) const {
-        cx<float> h = hi[i];
-        uint32_t l = lo[i];
+        const cx<float> h = gld(hi + i);
+        const uint32_t l = gld(lo + i);
         return {double(h.x) + double(bf16_to_f32(l & 0xFFFFu)), double(h.y) + double(bf16_to_f32(l >> 16))};
     }
     __device__ __forceinline__ void st(size_t i, cx<double> v) const {
-        float hx = float(v.x), hy = float(v.y);
-        float lx = float(v.x - double(hx)), ly = float(v.y - double(hy));
-        hi[i] = {hx, hy};
-        lo[i] = f32_to_bf16_rne(lx) | (f32_to_bf16_rne(ly) << 16);
+        const float hx = float(v.x), hy = float(v.y);
+        const float lx = float(v.x - double(hx)), ly = float(v.y - double(hy));
+        gst(hi + i, cx<float>{hx, hy});
+        gst(lo + i, uint32_t(f32_to_bf16_rne(lx) | (f32_to_bf16_rne(ly) << 16)));
     }
 };
 

@@ -156,7 +156,7 @@ p1_r2c(const Batch<DT> bt) {
     const int ug = xcd_unit();
     if (ug >= bt.count * units) return;
     const Prob<DT>& P = bt.p[ug / units];
-    const Work<DT> w1 = P.w1;
+    const Work<DT>& w1 = P.w1;
     const cx<Real>* __restrict__ tw = P.tw;
     const int t = threadIdx.x % C::T, ln = threadIdx.x / C::T;
     const size_t line = size_t(ug % units) * C::LC + ln;
@@ -216,7 +216,8 @@ p2_fwd(const Batch<DT> bt) {
     const int ug = xcd_unit();
     if (ug >= bt.count * units) return;
     const Prob<DT>& P = bt.p[ug / units];
-    const Work<DT> w1 = P.w1, w2 = P.w2;
+    const Work<DT>& w1 = P.w1;
+    const Work<DT>& w2 = P.w2;
     const cx<Real>* __restrict__ tw = P.tw;
     const int u = ug % units;
     const int i0 = u / tiles, tile = u % tiles;
@@ -276,7 +277,7 @@ p3_conv(const Batch<DT> bt) {
     const int ug = xcd_unit();
     if (ug >= bt.count * units) return;  // whole workgroup
     const Prob<DT>& P = bt.p[ug / units];
-    const Work<DT> w2 = P.w2;
+    const Work<DT>& w2 = P.w2;
     const typename C::Kt* __restrict__ K = P.K;
     const cx<Real>* __restrict__ tw = P.tw;
     const int u = ug % units;
@@ -347,7 +348,7 @@ p3_col0(const Batch<DT> bt) {
 
     if (int(blockIdx.x) >= bt.count * N) return;
     const Prob<DT>& P = bt.p[blockIdx.x / N];
-    const Work<DT> w2 = P.w2;
+    const Work<DT>& w2 = P.w2;
     const typename C::Kt* __restrict__ K = P.K;
     const typename C::Kt* __restrict__ Kb = P.Kb;
     const cx<Real>* __restrict__ tw = P.tw;
@@ -415,7 +416,8 @@ p4_inv(const Batch<DT> bt) {
     const int ug = xcd_unit();
     if (ug >= bt.count * units) return;
     const Prob<DT>& P = bt.p[ug / units];
-    const Work<DT> w1 = P.w1, w2 = P.w2;
+    const Work<DT>& w1 = P.w1;
+    const Work<DT>& w2 = P.w2;
     const cx<Real>* __restrict__ tw = P.tw;
     const int u = ug % units;
     const int i0 = u / tiles, tile = u % tiles;
@@ -454,31 +456,35 @@ p5_c2r(const Batch<DT> bt) {
     const int ug = xcd_unit();
     if (ug >= bt.count * units) return;
     const Prob<DT>& P = bt.p[ug / units];
-    const Work<DT> w1 = P.w1;
+    const Work<DT>& w1 = P.w1;
     Io* __restrict__ u = P.u;
     const cx<Real>* __restrict__ tw = P.tw;
     const int t = threadIdx.x % C::T, ln = threadIdx.x / C::T;
     const size_t line = size_t(ug % units) * C::LC + ln;
     const size_t base = line * N;
 
-    // Y[k] = (V[k] + conj V[n-k]) + i (V[k] - conj V[n-k]) w^-k; V[0], V[n] real and packed
+    // Y[k] = (V[k] + conj V[n-k]) + i (V[k] - conj V[n-k]) w^-k; V[0], V[n] real and packed.
+    // Each V is loaded once; the partner V[n-k] comes back through the line's
+    // LDS row (the first exchange of the transform waits before reusing it).
+    TwLds<Real> tl{sb + C::LC * C::NP};
+    tl.fill(tw, N, threadIdx.x, C::LC * C::T);
+    LdsRows<Real> lds{sb + ln * C::NP};
     cx<Real> d[F::E];
+#pragma unroll
+    for (int e = 0; e < F::E; ++e) d[e] = w1.ld(base + F::in_pos(t, e));
+#pragma unroll
+    for (int e = 0; e < F::E; ++e) lds.put(F::in_pos(t, e), d[e]);
+    __syncthreads();
 #pragma unroll
     for (int e = 0; e < F::E; ++e) {
         const int pos = F::in_pos(t, e);
         if (pos == 0) {
-            const cx<Real> V = w1.ld(base);
-            d[e] = {V.x + V.y, V.x - V.y};
+            d[e] = {d[e].x + d[e].y, d[e].x - d[e].y};
         } else {
-            const cx<Real> a = w1.ld(base + pos);
-            const cx<Real> b = conj(w1.ld(base + N - pos));
-            d[e] = (a + b) + rot<+1>(mul_conj(a - b, tw[pos]));
+            const cx<Real> b = conj(lds.get(N - pos));
+            d[e] = (d[e] + b) + rot<+1>(mul_conj(d[e] - b, tl(pos)));
         }
     }
-    TwLds<Real> tl{sb + C::LC * C::NP};
-    tl.fill(tw, N, threadIdx.x, C::LC * C::T);
-    if constexpr (F::S == 1) __syncthreads();
-    LdsRows<Real> lds{sb + ln * C::NP};
     F::run1(d, t, tl, lds);
     // z[j] = u[2j] + i u[2j+1]; only j < n/2 lies inside the box
 #pragma unroll
