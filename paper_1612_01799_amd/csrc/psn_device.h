@@ -219,9 +219,9 @@ template <class Lds>
 struct Single {
     Lds& l;
     template <class C>
-    __device__ __forceinline__ void put(int pos, const C (&v)[1]) { l.put(pos, v[0]); }
+    __device__ __forceinline__ void put2(int base, int off, const C (&v)[1]) { l.put2(base, off, v[0]); }
     template <class C>
-    __device__ __forceinline__ void get(int pos, C (&v)[1]) const { v[0] = l.get(pos); }
+    __device__ __forceinline__ void get2(int base, int off, C (&v)[1]) const { v[0] = l.get2(base, off); }
     __device__ __forceinline__ void sync() { l.sync(); }
 };
 
@@ -261,7 +261,8 @@ struct TeamFFT {
 
     // NC independent lines per thread advance together: one barrier pair per
     // exchange serves all of them.  `lds` stores the NC values of one position
-    // together (put/get of cx[NC]); `tw(m)` returns exp(-2 pi i m / 2N).
+    // together (put2/get2 of cx[NC] at position base + off, off a compile-time
+    // constant); `tw(m)` returns exp(-2 pi i m / 2N).
     template <int I, int NC, class Lds, class Tw>
     static __device__ __forceinline__ void stage(cx<Real> (&d)[NC][E], int t, const Tw& tw, Lds& lds) {
         if constexpr (I < S) {
@@ -272,7 +273,7 @@ struct TeamFFT {
 #pragma unroll
                 for (int e = 0; e < E; ++e) {
                     cx<Real> v[NC];
-                    lds.get(t + T * (e / R) + (e % R) * (N / R), v);
+                    lds.get2(t, T * (e / R) + (e % R) * (N / R), v);
 #pragma unroll
                     for (int c = 0; c < NC; ++c) d[c][e] = v[c];
                 }
@@ -299,11 +300,16 @@ struct TeamFFT {
                 lds.sync();
 #pragma unroll
                 for (int e = 0; e < E; ++e) {
-                    const int b = t + T * (e / R);
                     cx<Real> v[NC];
 #pragma unroll
                     for (int c = 0; c < NC; ++c) v[c] = d[c][e];
-                    lds.put((b / Ns) * Ns * R + (b % Ns) + (e % R) * Ns, v);
+                    if constexpr (T % Ns == 0) {
+                        // t's part and e's part of the position separate
+                        lds.put2((t / Ns) * Ns * R + t % Ns, T * (e / R) * R + (e % R) * Ns, v);
+                    } else {
+                        const int b = t + T * (e / R);
+                        lds.put2((b / Ns) * Ns * R + (b % Ns) + (e % R) * Ns, 0, v);
+                    }
                 }
                 lds.sync();
             }
@@ -346,6 +352,8 @@ struct LdsCols {
     int col;
     __device__ __forceinline__ void put(int pos, cx<Real> v) { buf[pos * stride + col] = v; }
     __device__ __forceinline__ cx<Real> get(int pos) const { return buf[pos * stride + col]; }
+    __device__ __forceinline__ void put2(int base, int off, cx<Real> v) { put(base + off, v); }
+    __device__ __forceinline__ cx<Real> get2(int base, int off) const { return get(base + off); }
     __device__ __forceinline__ void sync() { __syncthreads(); }
 };
 
@@ -366,6 +374,8 @@ struct LdsCols2 {
         v[0] = q[0];
         v[1] = q[1];
     }
+    __device__ __forceinline__ void put2(int base, int off, const cx<Real> (&v)[2]) { put(base + off, v); }
+    __device__ __forceinline__ void get2(int base, int off, cx<Real> (&v)[2]) const { get(base + off, v); }
     __device__ __forceinline__ void sync() { __syncthreads(); }
 };
 
@@ -375,8 +385,15 @@ template <class Real>
 struct LdsRows {
     cx<Real>* buf;
     __device__ __forceinline__ static int skew(int pos) { return pos + (pos >> 4); }
+    // skew(base + off) for a constant off: a multiple of 16 passes through the
+    // shift exactly (base + off >= 0), so only base's skew is computed
+    __device__ __forceinline__ static int skew2(int base, int off) {
+        return (off % 16 == 0) ? skew(base) + off + off / 16 : skew(base + off);
+    }
     __device__ __forceinline__ void put(int pos, cx<Real> v) { buf[skew(pos)] = v; }
     __device__ __forceinline__ cx<Real> get(int pos) const { return buf[skew(pos)]; }
+    __device__ __forceinline__ void put2(int base, int off, cx<Real> v) { buf[skew2(base, off)] = v; }
+    __device__ __forceinline__ cx<Real> get2(int base, int off) const { return buf[skew2(base, off)]; }
     __device__ __forceinline__ void sync() { __syncthreads(); }
 };
 
@@ -436,33 +453,50 @@ __device__ __forceinline__ void gst(cx<R>* p, cx<R> v) {
 __device__ __forceinline__ uint32_t gld(const uint32_t* p) { return *(const PSN_GLOBAL uint32_t*)(p); }
 __device__ __forceinline__ void gst(uint32_t* p, uint32_t v) { *(PSN_GLOBAL uint32_t*)(p) = v; }
 
+// ld/st(i) address element i; ld/st(ub, off) address element ub + off with ub
+// uniform over the wave and off a 32-bit lane offset, which keeps the lane
+// part of the address in one 32-bit register.
 template <>
 struct Work<DT_F32> {
     cx<float>* p;
     __device__ __forceinline__ cx<float> ld(size_t i) const { return gld(p + i); }
     __device__ __forceinline__ void st(size_t i, cx<float> v) const { gst(p + i, v); }
+    __device__ __forceinline__ cx<float> ld(size_t ub, uint32_t off) const { return gld((p + ub) + off); }
+    __device__ __forceinline__ void st(size_t ub, uint32_t off, cx<float> v) const { gst((p + ub) + off, v); }
 };
 template <>
 struct Work<DT_F64> {
     cx<double>* p;
     __device__ __forceinline__ cx<double> ld(size_t i) const { return gld(p + i); }
     __device__ __forceinline__ void st(size_t i, cx<double> v) const { gst(p + i, v); }
+    __device__ __forceinline__ cx<double> ld(size_t ub, uint32_t off) const { return gld((p + ub) + off); }
+    __device__ __forceinline__ void st(size_t ub, uint32_t off, cx<double> v) const { gst((p + ub) + off, v); }
 };
 // FP32 high part + bfloat16 low part (two per 32-bit word): 6 bytes per real.
 template <>
 struct Work<DT_SPLIT> {
     cx<float>* hi;
     uint32_t* lo;
-    __device__ __forceinline__ cx<double> ld(size_t i) const {
-        const cx<float> h = gld(hi + i);
-        const uint32_t l = gld(lo + i);
+    static __device__ __forceinline__ cx<double> join(cx<float> h, uint32_t l) {
         return {double(h.x) + double(bf16_to_f32(l & 0xFFFFu)), double(h.y) + double(bf16_to_f32(l >> 16))};
     }
+    static __device__ __forceinline__ uint32_t low_of(cx<double> v, cx<float> h) {
+        const float lx = float(v.x - double(h.x)), ly = float(v.y - double(h.y));
+        return uint32_t(f32_to_bf16_rne(lx) | (f32_to_bf16_rne(ly) << 16));
+    }
+    __device__ __forceinline__ cx<double> ld(size_t i) const { return join(gld(hi + i), gld(lo + i)); }
     __device__ __forceinline__ void st(size_t i, cx<double> v) const {
-        const float hx = float(v.x), hy = float(v.y);
-        const float lx = float(v.x - double(hx)), ly = float(v.y - double(hy));
-        gst(hi + i, cx<float>{hx, hy});
-        gst(lo + i, uint32_t(f32_to_bf16_rne(lx) | (f32_to_bf16_rne(ly) << 16)));
+        const cx<float> h{float(v.x), float(v.y)};
+        gst(hi + i, h);
+        gst(lo + i, low_of(v, h));
+    }
+    __device__ __forceinline__ cx<double> ld(size_t ub, uint32_t off) const {
+        return join(gld((hi + ub) + off), gld((lo + ub) + off));
+    }
+    __device__ __forceinline__ void st(size_t ub, uint32_t off, cx<double> v) const {
+        const cx<float> h{float(v.x), float(v.y)};
+        gst((hi + ub) + off, h);
+        gst((lo + ub) + off, low_of(v, h));
     }
 };
 

@@ -3,7 +3,9 @@
 //
 // Layout (C order, last index contiguous), M = 2n:
 //   rho, u : [i0][i1][i2]            n^3 reals
-//   W1     : [i0][i1][k2]            n^3 complex, k2 = 0..n-1
+//   W1     : [i0][k2/BL][i1][k2%BL]  n^3 complex, k2 = 0..n-1, tiled over k2
+//            (BL = the axis-1 column tile) so that an axis-1 workgroup's
+//            column block is one contiguous run
 //   W2     : n * M * n complex, blocked over k1 and tiled over k2 (W2Index)
 //            so that both the axis-1 passes (fixed i0, all k1) and the axis-0
 //            pass (fixed k1, all i0) read and write long contiguous runs
@@ -62,7 +64,7 @@ constexpr int rows_padded(int N) { return N + (N >> 4) + 1; }
 constexpr int pick_lines(int N, int T, int cxbytes) {
     int l = 256 / T;
     if (l < 1) l = 1;
-    while (l > 1 && ((N * N) % l != 0 || (l * rows_padded(N) + ((2 * N + 15) & ~15)) * cxbytes > kMaxLds)) l /= 2;
+    while (l > 1 && (N % l != 0 || (l * rows_padded(N) + ((2 * N + 15) & ~15)) * cxbytes > kMaxLds)) l /= 2;
     return l;
 }
 
@@ -91,6 +93,19 @@ struct W2Index {
     }
     // stride between consecutive i0 at fixed (k1, k2)
     static constexpr size_t s0 = size_t(N) * KB;
+};
+
+// W1 layout, tiled over k2: element (i0, i1, k2) lives at
+//   ((i0 * (N / BL) + k2 / BL) * N + i1) * BL + k2 % BL,
+// so the axis-1 passes (one i0, one tile of BL columns, all i1) move one
+// contiguous block and the axis-2 passes (a few lines i1 of one i0) move
+// runs of lines * BL elements.
+template <int N, int BL>
+struct W1Index {
+    static_assert(N % BL == 0, "");
+    static __device__ __forceinline__ size_t at(int i0, int i1, int k2) {
+        return ((size_t(i0) * (N / BL) + k2 / BL) * N + i1) * BL + k2 % BL;
+    }
 };
 
 template <int N, int DT>
@@ -143,6 +158,27 @@ __device__ __forceinline__ int xcd_unit() {
 // Grid size for `units` units dealt by xcd_unit().
 inline int xcd_grid(long units) { return int(8 * ((units + 7) / 8)); }
 
+// The LC * N W1 elements of an axis-2 workgroup in tile-contiguous order:
+// element j = tid + LC * T * q is line lj = j / BL % LC and column
+// k = j / (BL * LC) * BL + j % BL, so consecutive threads touch consecutive W1
+// addresses.  When BL divides T, k = k0 + T * q with lj and k0 fixed per thread.
+template <int N, int LC, int T, int BL>
+struct TileOrder {
+    static constexpr bool split = T % BL == 0;
+    static __device__ __forceinline__ void at(int tid, int q, int& lj, int& k0, int& off) {
+        if constexpr (split) {
+            lj = (tid / BL) % LC;
+            k0 = (tid / (BL * LC)) * BL + tid % BL;
+            off = T * q;
+        } else {
+            const int j = tid + LC * T * q;
+            lj = (j / BL) % LC;
+            k0 = (j / (BL * LC)) * BL + j % BL;
+            off = 0;
+        }
+    }
+};
+
 // ------------------------------------------------------------------ P1
 template <int N, int DT>
 __global__ void __launch_bounds__((Cfg<N, DT>::LC * Cfg<N, DT>::T))
@@ -159,8 +195,9 @@ p1_r2c(const Batch<DT> bt) {
     const Work<DT>& w1 = P.w1;
     const cx<Real>* __restrict__ tw = P.tw;
     const int t = threadIdx.x % C::T, ln = threadIdx.x / C::T;
-    const size_t line = size_t(ug % units) * C::LC + ln;
-    const typename C::Io* x = P.rho + line * N;
+    const int line0 = (ug % units) * C::LC;  // first line of the workgroup; all share i0
+    const int i0 = line0 / N, i1b = line0 % N;
+    const typename C::Io* x = P.rho + (size_t(line0) + ln) * N;
 
     // z[j] = x[2j] + i x[2j+1]; zero for j >= n/2 (the padding)
     cx<Real> d[F::E];
@@ -176,23 +213,32 @@ p1_r2c(const Batch<DT> bt) {
     F::run1(d, t, tl, lds);
     __syncthreads();
 #pragma unroll
-    for (int e = 0; e < F::E; ++e) lds.put(F::out_pos(t, e), d[e]);
+    for (int e = 0; e < F::E; ++e) lds.put2(t, F::out_pos(0, e), d[e]);  // out_pos(t, e) = t + out_pos(0, e)
     __syncthreads();
-    // X[k] = E[k] + w^k O[k], E = (Z[k] + conj Z[n-k])/2, O = (Z[k] - conj Z[n-k])/(2i)
+    // X[k] = E[k] + w^k O[k], E = (Z[k] + conj Z[n-k])/2, O = (Z[k] - conj Z[n-k])/(2i).
+    // Element j of the workgroup's LC * N outputs is (line j / BS % LC,
+    // k = j / (BS * LC) * BS + j % BS): consecutive threads write consecutive
+    // W1 addresses.
+    constexpr int BL = C::BS;
+    using W1I = W1Index<N, BL>;
+    using TO = TileOrder<N, C::LC, C::T, BL>;
 #pragma unroll
     for (int q = 0; q < F::E; ++q) {
-        const int k = t + C::T * q;
-        const cx<Real> Z = lds.get(k);
+        int lj, k0, off;
+        TO::at(int(threadIdx.x), q, lj, k0, off);
+        const int k = k0 + off;
+        const LdsRows<Real> row{sb + lj * C::NP};
+        const cx<Real> Z = row.get2(k0, off);
         cx<Real> X;
         if (k == 0) {
             X = {Z.x + Z.y, Z.x - Z.y};  // (X[0], X[n]) packed
         } else {
-            const cx<Real> Zr = conj(lds.get(N - k));
+            const cx<Real> Zr = conj(row.get2(N - k0, -off));
             const cx<Real> Ev = scale(Z + Zr, Real(0.5));
             const cx<Real> Od = rot<-1>(scale(Z - Zr, Real(0.5)));
             X = Ev + Od * tl(k);
         }
-        w1.st(line * N + k, X);
+        w1.st(W1I::at(i0, i1b + lj, k), X);
     }
 }
 
@@ -223,13 +269,13 @@ p2_fwd(const Batch<DT> bt) {
     const int i0 = u / tiles, tile = u % tiles;
     const int c = threadIdx.x % B, t = threadIdx.x / B;
     const int k2 = tile * B + c;
-    const size_t inb = size_t(i0) * N * N + k2;
+    using W1I = W1Index<N, B>;
 
     cx<Real> d[2][E], w[E];
 #pragma unroll
     for (int e = 0; e < E; ++e) {
         const int pos = F::in_pos(t, e);
-        d[0][e] = w1.ld(inb + size_t(pos) * N);
+        d[0][e] = w1.ld(W1I::at(i0, pos, k2));
         w[e] = tw[pos];
     }
     TwLds<Real> tl{stw};
@@ -247,32 +293,35 @@ p2_fwd(const Batch<DT> bt) {
 }
 
 // ------------------------------------------------------------------ P3
-// One workgroup = one row k1 of W2 and B adjacent columns k2.  The two parity
-// chains (even and odd k0) of each line advance in lockstep, stored side by
-// side in LDS, so one pair of barriers and one 16-byte access per element
-// serve both.  Workgroup ids are dealt to the XCDs round robin; each XCD gets
-// a contiguous run of units (unit = one row of one tile, rows k1 and M-k1 of a
-// tile back to back), so tiles sharing 128-byte lines and rows sharing a
-// kernel row meet in the same L2.  All global loads (data, the pre/post
-// twiddles of the odd chain and the kernel values) are issued before any
-// arithmetic; the stage twiddles come from a copy of the table in LDS.
-// Column 0 (the packed k2 = 0 / k2 = n pair) is left to p3_col0.
-template <int N, int DT, int B, int TT>
-__global__ void __launch_bounds__((B * TT))
+// One workgroup = SL rows of W2 and B adjacent columns k2.  With SL = 2 the
+// rows are k1 and M-k1, which share a kernel row and sit next to each other in
+// the W2 layout, so each i0 is one run of 2 * B elements; with SL = 1 the two
+// rows go to consecutive units instead.  The two parity chains (even and odd
+// k0) of each line advance in lockstep, stored side by side in LDS, so one pair
+// of barriers and one 16-byte access per element serve both.  Workgroup ids
+// are dealt to the XCDs round robin; each XCD gets a contiguous run of units,
+// so tiles sharing 128-byte lines and rows sharing a kernel row meet in the
+// same L2.  All global loads (data, the pre/post twiddles of the odd chain and
+// the kernel values) are issued before any arithmetic; the stage twiddles come
+// from a copy of the table in LDS.  Column 0 (the packed k2 = 0 / k2 = n pair)
+// is left to p3_col0.
+template <int N, int DT, int B, int TT, int SL>
+__global__ void __launch_bounds__((B * TT * SL))
 p3_conv(const Batch<DT> bt) {
     using C = Cfg<N, DT>;
     using Real = typename C::Real;
     using Ff = TeamFFT<N, TT, Real, -1, false>;
     using Fi = TeamFFT<N, TT, Real, +1, true>;
+    static_assert(SL == 1 || SL == 2, "one row or a row pair per workgroup");
     constexpr int E = Ff::E;
     constexpr int tiles = N / B;
-    constexpr int units = 2 * N * tiles;   // per problem: rows k1 and M-k1 of each (pair, tile)
+    constexpr int units = (2 / SL) * N * tiles;  // per problem
     using WI = W2Index<N, Cfg<N, DT>::BS>;
     static_assert(Cfg<N, DT>::BS % B == 0, "the axis-0 tile lies inside a W2 layout tile");
     constexpr size_t s0 = WI::s0;  // stride of i0 in W2
     extern __shared__ __align__(16) unsigned char smem[];
     cx<Real>* sb = reinterpret_cast<cx<Real>*>(smem);
-    cx<Real>* stw = sb + 2 * B * N;
+    cx<Real>* stw = sb + 2 * B * SL * N;
 
     const int ug = xcd_unit();
     if (ug >= bt.count * units) return;  // whole workgroup
@@ -281,32 +330,46 @@ p3_conv(const Batch<DT> bt) {
     const typename C::Kt* __restrict__ K = P.K;
     const cx<Real>* __restrict__ tw = P.tw;
     const int u = ug % units;
-    const int item = u >> 1, set = u & 1;
-    const int q = item / tiles, tile = item % tiles;
-    const int k1 = set == 0 ? q : (q == 0 ? N : 2 * N - q);
-    const int kt1 = k1 <= N ? k1 : 2 * N - k1;
-    const int c = threadIdx.x % B, t = threadIdx.x / B;
+    int q, tile, set;
+    if constexpr (SL == 1) {
+        const int item = u >> 1;
+        set = u & 1;
+        q = item / tiles;
+        tile = item % tiles;
+    } else {
+        q = u / tiles;
+        tile = u % tiles;
+        set = (threadIdx.x / B) & 1;
+    }
+    const int c = threadIdx.x % B, t = threadIdx.x / (B * SL);
     const int k2 = tile * B + c;
-    const size_t base = WI::at(0, k1, k2);
-    const typename C::Kt* Krow = K + size_t(kt1) * (N + 1) * N + k2;
+    // Addresses: a base uniform over the workgroup (row q, column tile * B)
+    // plus a 32-bit lane offset.  Row M-q sits BS elements after row q in the
+    // W2 layout; its kernel row is q as well, except for the pair (0, n).
+    static_assert(WI::s0 * N < (size_t(1) << 32) && size_t(N + 1) * (N + 1) * N < (size_t(1) << 32),
+                  "lane offsets fit 32 bits");
+    const size_t ub = WI::at(0, q, tile * B);
+    const uint32_t xl = uint32_t(c) + uint32_t(set) * Cfg<N, DT>::BS + uint32_t(t) * uint32_t(s0);
+    const typename C::Kt* Kq = K + (size_t(q) * (N + 1) * N + size_t(tile) * B);
+    const uint32_t kl = uint32_t(c) + ((set != 0 && q == 0) ? uint32_t(N) * (N + 1) * N : 0u);
+    auto xoff = [&](int e) { return xl + uint32_t(Ff::in_pos(0, e)) * uint32_t(s0); };
 
     cx<Real> x[E], w[E];
     Real ke[E], ko[E];
 #pragma unroll
     for (int e = 0; e < E; ++e) {
-        const int pos = Ff::in_pos(t, e);
-        x[e] = w2.ld(base + size_t(pos) * s0);
-        w[e] = tw[pos];
+        x[e] = w2.ld(ub, xoff(e));
+        w[e] = tw[Ff::in_pos(t, e)];
     }
 #pragma unroll
     for (int e = 0; e < E; ++e) {
         const int m = Ff::out_pos(t, e);
         const int a = 2 * m, b = 2 * m + 1;
-        ke[e] = Real(Krow[size_t(a <= N ? a : 2 * N - a) * N]);
-        ko[e] = Real(Krow[size_t(b <= N ? b : 2 * N - b) * N]);
+        ke[e] = Real(Kq[kl + uint32_t(a <= N ? a : 2 * N - a) * N]);
+        ko[e] = Real(Kq[kl + uint32_t(b <= N ? b : 2 * N - b) * N]);
     }
     TwLds<Real> tl{stw};
-    tl.fill(tw, N, threadIdx.x, B * TT);  // visible after the first exchange
+    tl.fill(tw, N, threadIdx.x, B * TT * SL);  // visible after the first exchange
 
     cx<Real> d[2][E];
 #pragma unroll
@@ -314,7 +377,7 @@ p3_conv(const Batch<DT> bt) {
         d[0][e] = x[e];
         d[1][e] = x[e] * w[e];
     }
-    LdsCols2<Real> lds{sb, B, c};
+    LdsCols2<Real> lds{sb, B * SL, int(threadIdx.x % (B * SL))};
     Ff::template run<2>(d, t, tl, lds);
 #pragma unroll
     for (int e = 0; e < E; ++e) {
@@ -324,8 +387,7 @@ p3_conv(const Batch<DT> bt) {
     Fi::template run<2>(d, t, tl, lds);
     if (k2 != 0) {
 #pragma unroll
-        for (int e = 0; e < E; ++e)
-            w2.st(base + size_t(Fi::out_pos(t, e)) * s0, d[0][e] + mul_conj(d[1][e], w[e]));
+        for (int e = 0; e < E; ++e) w2.st(ub, xoff(e), d[0][e] + mul_conj(d[1][e], w[e]));
     }
 }
 
@@ -423,7 +485,7 @@ p4_inv(const Batch<DT> bt) {
     const int i0 = u / tiles, tile = u % tiles;
     const int c = threadIdx.x % B, t = threadIdx.x / B;
     const int k2 = tile * B + c;
-    const size_t outb = size_t(i0) * N * N + k2;
+    using W1I = W1Index<N, B>;
 
     cx<Real> d[2][E], w[E];
 #pragma unroll
@@ -439,7 +501,7 @@ p4_inv(const Batch<DT> bt) {
     F::template run<2>(d, t, tl, lds);
 #pragma unroll
     for (int e = 0; e < E; ++e)
-        w1.st(outb + size_t(F::out_pos(t, e)) * N, d[0][e] + mul_conj(d[1][e], w[e]));
+        w1.st(W1I::at(i0, F::out_pos(t, e), k2), d[0][e] + mul_conj(d[1][e], w[e]));
 }
 
 // ------------------------------------------------------------------ P5
@@ -460,29 +522,46 @@ p5_c2r(const Batch<DT> bt) {
     Io* __restrict__ u = P.u;
     const cx<Real>* __restrict__ tw = P.tw;
     const int t = threadIdx.x % C::T, ln = threadIdx.x / C::T;
-    const size_t line = size_t(ug % units) * C::LC + ln;
-    const size_t base = line * N;
+    const int line0 = (ug % units) * C::LC;  // first line of the workgroup; all share i0
+    const int i0 = line0 / N, i1b = line0 % N;
+    const size_t base = (size_t(line0) + ln) * N;  // of this thread's line in u
 
     // Y[k] = (V[k] + conj V[n-k]) + i (V[k] - conj V[n-k]) w^-k; V[0], V[n] real and packed.
-    // Each V is loaded once; the partner V[n-k] comes back through the line's
-    // LDS row (the first exchange of the transform waits before reusing it).
+    // The workgroup's LC lines of W1 are read with consecutive threads on
+    // consecutive addresses (element j is line j / BS % LC, k = j / (BS * LC) * BS
+    // + j % BS) into the LDS rows; each line's team then takes V[k] and its
+    // partner V[n-k] from there (the first exchange of the transform waits
+    // before reusing the rows).
+    constexpr int BL = C::BS;
+    using W1I = W1Index<N, BL>;
     TwLds<Real> tl{sb + C::LC * C::NP};
     tl.fill(tw, N, threadIdx.x, C::LC * C::T);
-    LdsRows<Real> lds{sb + ln * C::NP};
+    using TO = TileOrder<N, C::LC, C::T, BL>;
     cx<Real> d[F::E];
 #pragma unroll
-    for (int e = 0; e < F::E; ++e) d[e] = w1.ld(base + F::in_pos(t, e));
+    for (int q = 0; q < F::E; ++q) {
+        int lj, k0, off;
+        TO::at(int(threadIdx.x), q, lj, k0, off);
+        d[q] = w1.ld(W1I::at(i0, i1b + lj, k0 + off));
+    }
 #pragma unroll
-    for (int e = 0; e < F::E; ++e) lds.put(F::in_pos(t, e), d[e]);
+    for (int q = 0; q < F::E; ++q) {
+        int lj, k0, off;
+        TO::at(int(threadIdx.x), q, lj, k0, off);
+        LdsRows<Real>{sb + lj * C::NP}.put2(k0, off, d[q]);
+    }
     __syncthreads();
+    LdsRows<Real> lds{sb + ln * C::NP};
 #pragma unroll
     for (int e = 0; e < F::E; ++e) {
         const int pos = F::in_pos(t, e);
+        const int pc = pos - t;  // compile-time part of the position
+        const cx<Real> a = lds.get2(t, pc);
         if (pos == 0) {
-            d[e] = {d[e].x + d[e].y, d[e].x - d[e].y};
+            d[e] = {a.x + a.y, a.x - a.y};
         } else {
-            const cx<Real> b = conj(lds.get(N - pos));
-            d[e] = (d[e] + b) + rot<+1>(mul_conj(d[e] - b, tl(pos)));
+            const cx<Real> b = conj(lds.get2(N - t, -pc));
+            d[e] = (a + b) + rot<+1>(mul_conj(a - b, tl(pos)));
         }
     }
     F::run1(d, t, tl, lds);
@@ -511,12 +590,13 @@ inline bool allow_lds(const void* fn, size_t bytes) {
 // does not fit (LDS, threads, radix plan) is replaced by candidate 0.
 struct TileV {
     int B, TT;
+    int SL = 1;  // rows per workgroup (the axis-0 pass only)
 };
 
 constexpr bool tile_ok(int N, TileV v, int cxbytes) {
-    return v.B >= 1 && v.TT >= 1 && N % v.B == 0 && N % v.TT == 0 && v.B * v.TT <= 1024 &&
-           (2 * v.B * N + ((2 * N + 15) & ~15)) * cxbytes <= kMaxLdsP3 && make_plan(N, N / v.TT).n > 0 &&
-           N / v.TT <= 20;
+    return v.B >= 1 && v.TT >= 1 && (v.SL == 1 || v.SL == 2) && N % v.B == 0 && N % v.TT == 0 &&
+           v.B * v.TT * v.SL <= 1024 && (2 * v.B * v.SL * N + ((2 * N + 15) & ~15)) * cxbytes <= kMaxLdsP3 &&
+           make_plan(N, N / v.TT).n > 0 && N / v.TT <= 20;
 }
 
 constexpr TileV pick_tile(int N, TileV v, TileV dflt, int cxbytes) { return tile_ok(N, v, cxbytes) ? v : dflt; }
@@ -531,9 +611,10 @@ struct Sched {
     static constexpr TileV d24{C::BS, C::T24}, d3{C::BP3, C::T3};
     // P2/P4 keep the W2 layout tile (B = BS); P3 tiles must divide it
     static constexpr TileV v24[3] = {d24, pick_tile(N, {C::BS, N / e16}, d24, C::CX), d24};
-    static constexpr TileV v3[3] = {
-        d3, pick_tile3(N, {C::BP3 / 2 >= 1 ? C::BP3 / 2 : 1, N / e8}, d3, C::CX, C::BS),
-        pick_tile3(N, {C::BP3, N / e16}, d3, C::CX, C::BS)};
+    // P3: one row per workgroup, the row pair k1, M-k1 per workgroup, or one row
+    // of a narrower tile (more workgroups per CU)
+    static constexpr TileV v3[3] = {d3, pick_tile3(N, {C::BP3, C::T3, 2}, d3, C::CX, C::BS),
+                                    pick_tile3(N, {C::BP3 / 2 >= 1 ? C::BP3 / 2 : 1, C::T3, 1}, d3, C::CX, C::BS)};
     static_assert(tile_ok(N, d24, C::CX) && tile_ok(N, d3, C::CX), "default tiles must fit");
 };
 
@@ -562,11 +643,13 @@ hipError_t launch_p4(const Batch<DT>& bt, hipStream_t s) {
 template <int N, int DT, int I>
 hipError_t launch_p3(const Batch<DT>& bt, hipStream_t s) {
     constexpr TileV v = Sched<N, DT>::v3[I];
-    const size_t lds = (size_t(2) * v.B * N + TwLds<typename Cfg<N, DT>::Real>::slots(N)) * Cfg<N, DT>::CX;
-    static const bool ok = allow_lds(reinterpret_cast<const void*>(&p3_conv<N, DT, v.B, v.TT>), lds);
+    const size_t lds =
+        (size_t(2) * v.B * v.SL * N + TwLds<typename Cfg<N, DT>::Real>::slots(N)) * Cfg<N, DT>::CX;
+    static const bool ok = allow_lds(reinterpret_cast<const void*>(&p3_conv<N, DT, v.B, v.TT, v.SL>), lds);
     if (!ok) return hipErrorInvalidConfiguration;
-    hipLaunchKernelGGL((p3_conv<N, DT, v.B, v.TT>), dim3(xcd_grid(long(bt.count) * 2 * N * (N / v.B))),
-                       dim3(v.B * v.TT), lds, s, bt);
+    hipLaunchKernelGGL((p3_conv<N, DT, v.B, v.TT, v.SL>),
+                       dim3(xcd_grid(long(bt.count) * (2 / v.SL) * N * (N / v.B))), dim3(v.B * v.TT * v.SL), lds, s,
+                       bt);
     return hipSuccess;
 }
 
