@@ -167,9 +167,19 @@ struct RadixPlan {
 // a whole number of butterflies.
 constexpr RadixPlan make_plan(int N, int E) {
     RadixPlan p{0, {}};
+    if (N < 1 || E < 1 || N % E != 0) return RadixPlan{-1, {}};
     int rem = N;
-    while (rem % 5 == 0) { p.r[p.n++] = 5; rem /= 5; }
-    while (rem % 3 == 0) { p.r[p.n++] = 3; rem /= 3; }
+    // every radix must divide E: a thread runs E / R butterflies of radix R per stage
+    while (rem % 5 == 0) {
+        if (E % 5 != 0) return RadixPlan{-1, {}};
+        p.r[p.n++] = 5;
+        rem /= 5;
+    }
+    while (rem % 3 == 0) {
+        if (E % 3 != 0) return RadixPlan{-1, {}};
+        p.r[p.n++] = 3;
+        rem /= 3;
+    }
     int e2 = E & -E;
     while (rem > 1) {
         int R = 16;
@@ -242,6 +252,12 @@ struct TeamFFT {
     static constexpr int S = plan.n;
     static_assert(N % T == 0, "team must divide the line");
     static_assert(S > 0, "no radix plan for this size");
+    static constexpr bool radices_divide_e() {
+        for (int i = 0; i < S; ++i)
+            if (E % plan.r[i] != 0) return false;
+        return true;
+    }
+    static_assert(radices_divide_e(), "every radix must divide the elements per thread");
 
     static constexpr int radix(int i) { return REV ? plan.r[S - 1 - i] : plan.r[i]; }
     static constexpr int span(int i) {
