@@ -206,6 +206,7 @@ constexpr int elems_per_thread(int N, int real_bytes) {
 // exp(-2 pi i m / 2N) for m in [0, 2N)
 template <class Real>
 struct TwGlobal {
+    static constexpr bool kRows = false;
     const cx<Real>* __restrict__ p;
     __device__ __forceinline__ cx<Real> operator()(int m) const { return p[m]; }
 };
@@ -214,6 +215,7 @@ struct TwGlobal {
 // power-of-two stride apart, which would otherwise fall into one bank.
 template <class Real>
 struct TwLds {
+    static constexpr bool kRows = false;
     cx<Real>* p;
     static constexpr int slots(int N) { return (2 * N + 15) & ~15; }
     __device__ __forceinline__ static int at(int m) { return m ^ ((m >> 4) & 15); }
@@ -224,9 +226,18 @@ struct TwLds {
     }
 };
 
+// Per-stage twiddle rows in LDS, laid out by TeamFFT::fill_rows: a thread
+// reads all R - 1 factors of a stage from one row.
+template <class Real>
+struct TwRows {
+    static constexpr bool kRows = true;
+    const cx<Real>* p;
+};
+
 // Adapts a one-value LDS view to the cx[1] interface of TeamFFT::stage.
 template <class Lds>
 struct Single {
+    static constexpr bool kSeq = false;
     Lds& l;
     template <class C>
     __device__ __forceinline__ void put2(int base, int off, const C (&v)[1]) { l.put2(base, off, v[0]); }
@@ -268,6 +279,50 @@ struct TeamFFT {
     static constexpr int R0 = radix(0);
     static constexpr int RL = radix(S - 1);
 
+    // Twiddle rows: stage i (span Ns = span(i) > 1, radix R) keeps, for each
+    // k < Ns, the factors exp(-2 pi i r k step / 2N), r = 1..R-1, step =
+    // 2N / (Ns R), in a row of row_pitch(i) entries (odd, so that rows of
+    // neighbouring k fall into different banks); the stages are packed in
+    // order.  A thread's k for a stage is t % Ns or t plus a constant (see
+    // row_k), so one row address per stage serves all its twiddles.
+    static constexpr int row_pitch(int i) { return (radix(i) - 1) | 1; }
+    static constexpr int rows_offset(int i) {
+        int o = 0;
+        for (int q = 1; q < i; ++q) o += span(q) * row_pitch(q);
+        return o;
+    }
+    static constexpr int rows_size() { return rows_offset(S); }  // entries
+    // true when both transforms use the same rows (same radices in the same order)
+    template <class F2>
+    static constexpr bool same_rows() {
+        if (F2::S != S) return false;
+        for (int i = 0; i < S; ++i)
+            if (F2::radix(i) != radix(i)) return false;
+        return true;
+    }
+    // cooperative fill from the 2N-entry table tw2n (global); visible after the next barrier
+    template <int I = 1>
+    static __device__ __forceinline__ void fill_rows(cx<Real>* rows, const cx<Real>* __restrict__ tw2n, int tid,
+                                                     int nthreads) {
+        if constexpr (I < S) {
+            constexpr int Ns = span(I), R = radix(I), RP = row_pitch(I), step = 2 * N / (Ns * R);
+            cx<Real>* row0 = rows + rows_offset(I);
+            for (int idx = tid; idx < Ns * RP; idx += nthreads) {
+                const int k = idx / RP, r = idx % RP + 1;
+                row0[idx] = r < R ? tw2n[r * k * step] : cx<Real>{Real(0), Real(0)};
+            }
+            fill_rows<I + 1>(rows, tw2n, tid, nthreads);
+        }
+    }
+    // k of group s of thread t in stage i, (t + T s) mod Ns, written so that
+    // its t part and its s part separate where the sizes allow
+    template <int Ns>
+    static __device__ __forceinline__ int row_k(int t, int s) {
+        if constexpr (T % Ns == 0) return t % Ns;
+        else if constexpr (Ns % T == 0) return t + T * (s % (Ns / T));
+        else return (t + T * s) % Ns;
+    }
+
     static __device__ __forceinline__ int in_pos(int t, int e) {
         return t + T * (e / R0) + (e % R0) * (N / R0);
     }
@@ -285,7 +340,7 @@ struct TeamFFT {
             constexpr int R = radix(I);
             constexpr int Ns = span(I);
             constexpr int twstep = 2 * N / (Ns * R);
-            if constexpr (I > 0) {
+            if constexpr (I > 0 && !Lds::kSeq) {
 #pragma unroll
                 for (int e = 0; e < E; ++e) {
                     cx<Real> v[NC];
@@ -298,9 +353,15 @@ struct TeamFFT {
             for (int s = 0; s < E / R; ++s) {
                 cx<Real> w[R];
                 if constexpr (Ns > 1) {
-                    const int k = (t + T * s) % Ns;
+                    if constexpr (Tw::kRows) {
+                        const cx<Real>* row = tw.p + rows_offset(I) + row_k<Ns>(t, s) * row_pitch(I);
 #pragma unroll
-                    for (int r = 1; r < R; ++r) w[r] = tw(r * k * twstep);
+                        for (int r = 1; r < R; ++r) w[r] = row[r - 1];
+                    } else {
+                        const int k = (t + T * s) % Ns;
+#pragma unroll
+                        for (int r = 1; r < R; ++r) w[r] = tw(r * k * twstep);
+                    }
                 }
 #pragma unroll
                 for (int c = 0; c < NC; ++c) {
@@ -313,21 +374,46 @@ struct TeamFFT {
                 }
             }
             if constexpr (I + 1 < S) {
-                lds.sync();
-#pragma unroll
-                for (int e = 0; e < E; ++e) {
-                    cx<Real> v[NC];
-#pragma unroll
-                    for (int c = 0; c < NC; ++c) v[c] = d[c][e];
+                // output position of slot e as (per-thread base, constant offset)
+                auto put_at = [&](int e, int& base, int& off) {
                     if constexpr (T % Ns == 0) {
-                        // t's part and e's part of the position separate
-                        lds.put2((t / Ns) * Ns * R + t % Ns, T * (e / R) * R + (e % R) * Ns, v);
+                        base = (t / Ns) * Ns * R + t % Ns;
+                        off = T * (e / R) * R + (e % R) * Ns;
                     } else {
                         const int b = t + T * (e / R);
-                        lds.put2((b / Ns) * Ns * R + (b % Ns) + (e % R) * Ns, 0, v);
+                        base = (b / Ns) * Ns * R + (b % Ns) + (e % R) * Ns;
+                        off = 0;
                     }
+                };
+                if constexpr (Lds::kSeq) {
+                    // one chain at a time through a one-chain buffer
+                    constexpr int R2 = radix(I + 1);
+#pragma unroll
+                    for (int c = 0; c < NC; ++c) {
+                        lds.sync();
+#pragma unroll
+                        for (int e = 0; e < E; ++e) {
+                            int base, off;
+                            put_at(e, base, off);
+                            lds.put1(base, off, d[c][e]);
+                        }
+                        lds.sync();
+#pragma unroll
+                        for (int e = 0; e < E; ++e) d[c][e] = lds.get1(t, T * (e / R2) + (e % R2) * (N / R2));
+                    }
+                } else {
+                    lds.sync();
+#pragma unroll
+                    for (int e = 0; e < E; ++e) {
+                        cx<Real> v[NC];
+#pragma unroll
+                        for (int c = 0; c < NC; ++c) v[c] = d[c][e];
+                        int base, off;
+                        put_at(e, base, off);
+                        lds.put2(base, off, v);
+                    }
+                    lds.sync();
                 }
-                lds.sync();
             }
             stage<I + 1, NC>(d, t, tw, lds);
         }
@@ -363,6 +449,7 @@ struct TeamFFT {
 // Strided passes: lines are columns of a tile, element-major, column fastest.
 template <class Real>
 struct LdsCols {
+    static constexpr bool kSeq = false;
     cx<Real>* buf;
     int stride;  // columns per element row
     int col;
@@ -377,6 +464,7 @@ struct LdsCols {
 // column next, chain fastest, so one 16-byte (FP32) access moves both chains.
 template <class Real>
 struct LdsCols2 {
+    static constexpr bool kSeq = false;
     cx<Real>* buf;
     int stride;  // columns per element row
     int col;
@@ -395,10 +483,25 @@ struct LdsCols2 {
     __device__ __forceinline__ void sync() { __syncthreads(); }
 };
 
+// Strided passes, two chains per line exchanged one after the other through a
+// one-chain buffer: half the LDS of LdsCols2 per column, two more barriers per
+// exchange.
+template <class Real>
+struct LdsColsSeq {
+    static constexpr bool kSeq = true;
+    cx<Real>* buf;
+    int stride;  // columns per element row
+    int col;
+    __device__ __forceinline__ void put1(int base, int off, cx<Real> v) { buf[(base + off) * stride + col] = v; }
+    __device__ __forceinline__ cx<Real> get1(int base, int off) const { return buf[(base + off) * stride + col]; }
+    __device__ __forceinline__ void sync() { __syncthreads(); }
+};
+
 // Contiguous passes: one row per line, with one pad slot every 16 elements so
 // strided butterfly writes spread over the banks.
 template <class Real>
 struct LdsRows {
+    static constexpr bool kSeq = false;
     cx<Real>* buf;
     __device__ __forceinline__ static int skew(int pos) { return pos + (pos >> 4); }
     // skew(base + off) for a constant off: a multiple of 16 passes through the

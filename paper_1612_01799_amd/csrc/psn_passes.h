@@ -33,6 +33,8 @@
 #include "psn_device.h"
 #include "psn_internal.h"
 
+#include <type_traits>
+
 namespace psn {
 
 constexpr int kMaxLds = 65536;       // per workgroup for the one-chain passes
@@ -61,6 +63,8 @@ constexpr int pick_cols_p3_div(int N, int bmax, int cxbytes, int T, int layout_t
 
 constexpr int rows_padded(int N) { return N + (N >> 4) + 1; }
 
+// lines per workgroup of the contiguous passes; their LDS holds the lines and
+// the 2N-entry twiddle table
 constexpr int pick_lines(int N, int T, int cxbytes) {
     int l = 256 / T;
     if (l < 1) l = 1;
@@ -245,8 +249,12 @@ p1_r2c(const Batch<DT> bt) {
 // ------------------------------------------------------------------ P2
 // Unit = (i0, tile of B columns k2).  Both outputs of a line (DFT_n of x and
 // of x w^j) are computed in lockstep from the same loads.
-template <int N, int DT, int B, int TT>
-__global__ void __launch_bounds__((B * TT))
+// LDS view of the strided passes: both chains side by side, or one at a time
+template <class Real, bool SEQ>
+using ChainLds = std::conditional_t<SEQ, LdsColsSeq<Real>, LdsCols2<Real>>;
+
+template <int N, int DT, int B, int TT, bool SEQ>
+__global__ void __launch_bounds__((B * TT), (SEQ ? 3 : 1))
 p2_fwd(const Batch<DT> bt) {
     using C = Cfg<N, DT>;
     using Real = typename C::Real;
@@ -258,7 +266,7 @@ p2_fwd(const Batch<DT> bt) {
     constexpr int units = N * tiles;  // per problem
     extern __shared__ __align__(16) unsigned char smem[];
     cx<Real>* sb = reinterpret_cast<cx<Real>*>(smem);
-    cx<Real>* stw = sb + 2 * B * N;
+    cx<Real>* stw = sb + (SEQ ? 1 : 2) * B * N;
     const int ug = xcd_unit();
     if (ug >= bt.count * units) return;
     const Prob<DT>& P = bt.p[ug / units];
@@ -282,7 +290,7 @@ p2_fwd(const Batch<DT> bt) {
     tl.fill(tw, N, threadIdx.x, B * TT);  // visible after the first exchange
 #pragma unroll
     for (int e = 0; e < E; ++e) d[1][e] = d[0][e] * w[e];
-    LdsCols2<Real> lds{sb, B, c};
+    ChainLds<Real, SEQ> lds{sb, B, c};
     F::template run<2>(d, t, tl, lds);
 #pragma unroll
     for (int e = 0; e < E; ++e) {
@@ -305,8 +313,13 @@ p2_fwd(const Batch<DT> bt) {
 // the kernel values) are issued before any arithmetic; the stage twiddles come
 // from a copy of the table in LDS.  Column 0 (the packed k2 = 0 / k2 = n pair)
 // is left to p3_col0.
-template <int N, int DT, int B, int TT, int SL>
-__global__ void __launch_bounds__((B * TT * SL))
+template <int N>
+struct P3Rows {
+    static constexpr bool value = N >= 512;
+};
+
+template <int N, int DT, int B, int TT, int SL, bool SEQ>
+__global__ void __launch_bounds__((B * TT * SL), (SEQ ? 3 : 1))
 p3_conv(const Batch<DT> bt) {
     using C = Cfg<N, DT>;
     using Real = typename C::Real;
@@ -321,7 +334,7 @@ p3_conv(const Batch<DT> bt) {
     constexpr size_t s0 = WI::s0;  // stride of i0 in W2
     extern __shared__ __align__(16) unsigned char smem[];
     cx<Real>* sb = reinterpret_cast<cx<Real>*>(smem);
-    cx<Real>* stw = sb + 2 * B * SL * N;
+    cx<Real>* stw = sb + (SEQ ? 1 : 2) * B * SL * N;
 
     const int ug = xcd_unit();
     if (ug >= bt.count * units) return;  // whole workgroup
@@ -368,8 +381,18 @@ p3_conv(const Batch<DT> bt) {
         ke[e] = Real(Kq[kl + uint32_t(a <= N ? a : 2 * N - a) * N]);
         ko[e] = Real(Kq[kl + uint32_t(b <= N ? b : 2 * N - b) * N]);
     }
+    // Stage twiddles: per-stage rows of both transforms (shared when their
+    // radices match) for n >= 512, where the saved index arithmetic outweighs
+    // the scattered reads that fill them; else the swizzled 2N-entry table.
+    constexpr bool kRows = P3Rows<N>::value;
+    cx<Real>* rows_i = stw + (Ff::template same_rows<Fi>() ? 0 : Ff::rows_size());
     TwLds<Real> tl{stw};
-    tl.fill(tw, N, threadIdx.x, B * TT * SL);  // visible after the first exchange
+    if constexpr (kRows) {
+        Ff::fill_rows(stw, tw, threadIdx.x, B * TT * SL);  // visible after the first exchange
+        if constexpr (!Ff::template same_rows<Fi>()) Fi::fill_rows(rows_i, tw, threadIdx.x, B * TT * SL);
+    } else {
+        tl.fill(tw, N, threadIdx.x, B * TT * SL);
+    }
 
     cx<Real> d[2][E];
 #pragma unroll
@@ -377,14 +400,16 @@ p3_conv(const Batch<DT> bt) {
         d[0][e] = x[e];
         d[1][e] = x[e] * w[e];
     }
-    LdsCols2<Real> lds{sb, B * SL, int(threadIdx.x % (B * SL))};
-    Ff::template run<2>(d, t, tl, lds);
+    ChainLds<Real, SEQ> lds{sb, B * SL, int(threadIdx.x % (B * SL))};
+    if constexpr (kRows) Ff::template run<2>(d, t, TwRows<Real>{stw}, lds);
+    else Ff::template run<2>(d, t, tl, lds);
 #pragma unroll
     for (int e = 0; e < E; ++e) {
         d[0][e] = scale(d[0][e], ke[e]);
         d[1][e] = scale(d[1][e], ko[e]);
     }
-    Fi::template run<2>(d, t, tl, lds);
+    if constexpr (kRows) Fi::template run<2>(d, t, TwRows<Real>{rows_i}, lds);
+    else Fi::template run<2>(d, t, tl, lds);
     if (k2 != 0) {
 #pragma unroll
         for (int e = 0; e < E; ++e) w2.st(ub, xoff(e), d[0][e] + mul_conj(d[1][e], w[e]));
@@ -461,8 +486,8 @@ p3_col0(const Batch<DT> bt) {
 // ------------------------------------------------------------------ P4
 // Unit = (i0, tile of B columns k2).  The even and odd rows of a line are
 // inverted in lockstep and combined as y = y_even + w^-j y_odd.
-template <int N, int DT, int B, int TT>
-__global__ void __launch_bounds__((B * TT))
+template <int N, int DT, int B, int TT, bool SEQ>
+__global__ void __launch_bounds__((B * TT), (SEQ ? 3 : 1))
 p4_inv(const Batch<DT> bt) {
     using C = Cfg<N, DT>;
     using Real = typename C::Real;
@@ -474,7 +499,7 @@ p4_inv(const Batch<DT> bt) {
     constexpr int units = N * tiles;  // per problem
     extern __shared__ __align__(16) unsigned char smem[];
     cx<Real>* sb = reinterpret_cast<cx<Real>*>(smem);
-    cx<Real>* stw = sb + 2 * B * N;
+    cx<Real>* stw = sb + (SEQ ? 1 : 2) * B * N;
     const int ug = xcd_unit();
     if (ug >= bt.count * units) return;
     const Prob<DT>& P = bt.p[ug / units];
@@ -497,7 +522,7 @@ p4_inv(const Batch<DT> bt) {
     }
     TwLds<Real> tl{stw};
     tl.fill(tw, N, threadIdx.x, B * TT);  // visible after the first exchange
-    LdsCols2<Real> lds{sb, B, c};
+    ChainLds<Real, SEQ> lds{sb, B, c};
     F::template run<2>(d, t, tl, lds);
 #pragma unroll
     for (int e = 0; e < E; ++e)
@@ -590,12 +615,14 @@ inline bool allow_lds(const void* fn, size_t bytes) {
 // does not fit (LDS, threads, radix plan) is replaced by candidate 0.
 struct TileV {
     int B, TT;
-    int SL = 1;  // rows per workgroup (the axis-0 pass only)
+    int SL = 1;        // rows per workgroup (the axis-0 pass only)
+    bool SEQ = false;  // exchange the two chains one at a time (half the LDS)
 };
 
 constexpr bool tile_ok(int N, TileV v, int cxbytes) {
     return v.B >= 1 && v.TT >= 1 && (v.SL == 1 || v.SL == 2) && N % v.B == 0 && N % v.TT == 0 &&
-           v.B * v.TT * v.SL <= 1024 && (2 * v.B * v.SL * N + ((2 * N + 15) & ~15)) * cxbytes <= kMaxLdsP3 &&
+           v.B * v.TT * v.SL <= 1024 &&
+           ((v.SEQ ? 1 : 2) * v.B * v.SL * N + ((2 * N + 15) & ~15)) * cxbytes <= kMaxLdsP3 &&
            make_plan(N, N / v.TT).n > 0 && N / v.TT <= 20;
 }
 
@@ -610,21 +637,37 @@ struct Sched {
     static constexpr int e8 = elems_per_thread(N, 8), e16 = elems_per_thread(N, 4);
     static constexpr TileV d24{C::BS, C::T24}, d3{C::BP3, C::T3};
     // P2/P4 keep the W2 layout tile (B = BS); P3 tiles must divide it
-    static constexpr TileV v24[3] = {d24, pick_tile(N, {C::BS, N / e16}, d24, C::CX), d24};
+    static constexpr TileV v24[3] = {d24, pick_tile(N, {C::BS, N / e16}, d24, C::CX),
+                                     pick_tile(N, {C::BS, C::T24, 1, true}, d24, C::CX)};
     // P3: one row per workgroup, the row pair k1, M-k1 per workgroup, or one row
-    // of a narrower tile (more workgroups per CU)
+    // with the chains exchanged one at a time
     static constexpr TileV v3[3] = {d3, pick_tile3(N, {C::BP3, C::T3, 2}, d3, C::CX, C::BS),
-                                    pick_tile3(N, {C::BP3 / 2 >= 1 ? C::BP3 / 2 : 1, C::T3, 1}, d3, C::CX, C::BS)};
+                                    pick_tile3(N, {C::BP3, C::T3, 1, true}, d3, C::CX, C::BS)};
     static_assert(tile_ok(N, d24, C::CX) && tile_ok(N, d3, C::CX), "default tiles must fit");
 };
+
+// LDS of the strided passes: the exchange area plus the stage twiddle rows
+template <int N, int DT, int B, int TT, bool SEQ>
+constexpr size_t lds_p24() {
+    return (size_t(SEQ ? 1 : 2) * B * N + TwLds<typename Cfg<N, DT>::Real>::slots(N)) * Cfg<N, DT>::CX;
+}
+template <int N, int DT, int B, int TT, int SL, bool SEQ>
+constexpr size_t lds_p3() {
+    using Real = typename Cfg<N, DT>::Real;
+    using Ff = TeamFFT<N, TT, Real, -1, false>;
+    using Fi = TeamFFT<N, TT, Real, +1, true>;
+    const size_t rows = P3Rows<N>::value ? Ff::rows_size() + (Ff::template same_rows<Fi>() ? 0 : Fi::rows_size())
+                                         : TwLds<Real>::slots(N);
+    return (size_t(SEQ ? 1 : 2) * B * SL * N + rows) * Cfg<N, DT>::CX;
+}
 
 template <int N, int DT, int I>
 hipError_t launch_p2(const Batch<DT>& bt, hipStream_t s) {
     constexpr TileV v = Sched<N, DT>::v24[I];
-    const size_t lds = (size_t(2) * v.B * N + TwLds<typename Cfg<N, DT>::Real>::slots(N)) * Cfg<N, DT>::CX;
-    static const bool ok = allow_lds(reinterpret_cast<const void*>(&p2_fwd<N, DT, v.B, v.TT>), lds);
+    const size_t lds = lds_p24<N, DT, v.B, v.TT, v.SEQ>();
+    static const bool ok = allow_lds(reinterpret_cast<const void*>(&p2_fwd<N, DT, v.B, v.TT, v.SEQ>), lds);
     if (!ok) return hipErrorInvalidConfiguration;
-    hipLaunchKernelGGL((p2_fwd<N, DT, v.B, v.TT>), dim3(xcd_grid(long(bt.count) * N * (N / v.B))), dim3(v.B * v.TT),
+    hipLaunchKernelGGL((p2_fwd<N, DT, v.B, v.TT, v.SEQ>), dim3(xcd_grid(long(bt.count) * N * (N / v.B))), dim3(v.B * v.TT),
                        lds, s, bt);
     return hipSuccess;
 }
@@ -632,10 +675,10 @@ hipError_t launch_p2(const Batch<DT>& bt, hipStream_t s) {
 template <int N, int DT, int I>
 hipError_t launch_p4(const Batch<DT>& bt, hipStream_t s) {
     constexpr TileV v = Sched<N, DT>::v24[I];
-    const size_t lds = (size_t(2) * v.B * N + TwLds<typename Cfg<N, DT>::Real>::slots(N)) * Cfg<N, DT>::CX;
-    static const bool ok = allow_lds(reinterpret_cast<const void*>(&p4_inv<N, DT, v.B, v.TT>), lds);
+    const size_t lds = lds_p24<N, DT, v.B, v.TT, v.SEQ>();
+    static const bool ok = allow_lds(reinterpret_cast<const void*>(&p4_inv<N, DT, v.B, v.TT, v.SEQ>), lds);
     if (!ok) return hipErrorInvalidConfiguration;
-    hipLaunchKernelGGL((p4_inv<N, DT, v.B, v.TT>), dim3(xcd_grid(long(bt.count) * N * (N / v.B))), dim3(v.B * v.TT),
+    hipLaunchKernelGGL((p4_inv<N, DT, v.B, v.TT, v.SEQ>), dim3(xcd_grid(long(bt.count) * N * (N / v.B))), dim3(v.B * v.TT),
                        lds, s, bt);
     return hipSuccess;
 }
@@ -643,11 +686,10 @@ hipError_t launch_p4(const Batch<DT>& bt, hipStream_t s) {
 template <int N, int DT, int I>
 hipError_t launch_p3(const Batch<DT>& bt, hipStream_t s) {
     constexpr TileV v = Sched<N, DT>::v3[I];
-    const size_t lds =
-        (size_t(2) * v.B * v.SL * N + TwLds<typename Cfg<N, DT>::Real>::slots(N)) * Cfg<N, DT>::CX;
-    static const bool ok = allow_lds(reinterpret_cast<const void*>(&p3_conv<N, DT, v.B, v.TT, v.SL>), lds);
+    const size_t lds = lds_p3<N, DT, v.B, v.TT, v.SL, v.SEQ>();
+    static const bool ok = allow_lds(reinterpret_cast<const void*>(&p3_conv<N, DT, v.B, v.TT, v.SL, v.SEQ>), lds);
     if (!ok) return hipErrorInvalidConfiguration;
-    hipLaunchKernelGGL((p3_conv<N, DT, v.B, v.TT, v.SL>),
+    hipLaunchKernelGGL((p3_conv<N, DT, v.B, v.TT, v.SL, v.SEQ>),
                        dim3(xcd_grid(long(bt.count) * (2 / v.SL) * N * (N / v.B))), dim3(v.B * v.TT * v.SL), lds, s,
                        bt);
     return hipSuccess;
@@ -706,28 +748,31 @@ hipError_t tune_n(const Batch<DT>& bt, hipStream_t s, int* best24, int* best3) {
     hipEvent_t a = nullptr, b = nullptr;
     hipError_t e = hipEventCreate(&a);
     if (e == hipSuccess) e = hipEventCreate(&b);
+    // one timed launch sequence
     auto timed = [&](auto&& launch, float* ms) -> hipError_t {
-        float best = 1e30f;
-        for (int r = 0; r < 4; ++r) {
-            hipError_t le = hipEventRecord(a, s);
-            if (le == hipSuccess) le = launch();
-            if (le == hipSuccess) le = hipEventRecord(b, s);
-            if (le == hipSuccess) le = hipEventSynchronize(b);
-            float t = 0.f;
-            if (le == hipSuccess) le = hipEventElapsedTime(&t, a, b);
-            if (le != hipSuccess) return le;
-            if (r > 0 && t < best) best = t;  // first run warms up
-        }
-        *ms = best;
-        return hipSuccess;
+        hipError_t le = hipEventRecord(a, s);
+        if (le == hipSuccess) le = launch();
+        if (le == hipSuccess) le = hipEventRecord(b, s);
+        if (le == hipSuccess) le = hipEventSynchronize(b);
+        if (le == hipSuccess) le = hipEventElapsedTime(ms, a, b);
+        return le;
     };
+    // Candidates are timed in interleaved rounds (so clock changes hit all of
+    // them alike); each keeps its best time; round 0 only warms up.
     float t24[3] = {1e30f, 1e30f, 1e30f}, t3[3] = {1e30f, 1e30f, 1e30f};
-    for (int v = 0; v < 3 && e == hipSuccess; ++v) {
-        e = timed([&] {
-                hipError_t x = launch_p24<N, DT>(bt, s, v, true);
-                return x == hipSuccess ? launch_p24<N, DT>(bt, s, v, false) : x;
-            }, &t24[v]);
-        if (e == hipSuccess) e = timed([&] { return launch_p3v<N, DT>(bt, s, v); }, &t3[v]);
+    for (int round = 0; round < 7 && e == hipSuccess; ++round) {
+        for (int v = 0; v < 3 && e == hipSuccess; ++v) {
+            float x = 0.f, y = 0.f;
+            e = timed([&] {
+                    hipError_t r = launch_p24<N, DT>(bt, s, v, true);
+                    return r == hipSuccess ? launch_p24<N, DT>(bt, s, v, false) : r;
+                }, &x);
+            if (e == hipSuccess) e = timed([&] { return launch_p3v<N, DT>(bt, s, v); }, &y);
+            if (e == hipSuccess && round > 0) {
+                t24[v] = x < t24[v] ? x : t24[v];
+                t3[v] = y < t3[v] ? y : t3[v];
+            }
+        }
     }
     if (a) (void)hipEventDestroy(a);
     if (b) (void)hipEventDestroy(b);
