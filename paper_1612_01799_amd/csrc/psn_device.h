@@ -43,6 +43,22 @@ __device__ __forceinline__ cx<R> twmul(cx<R> a, cx<R> w) {
     if constexpr (DIR < 0) return a * w;
     else return mul_conj(a, w);
 }
+template <class R>
+__device__ __forceinline__ R fmad(R a, R b, R c) {
+    if constexpr (sizeof(R) == 4) return __builtin_fmaf(a, b, c);
+    else return __builtin_fma(a, b, c);
+}
+// c + a * w (forward) or c + a * conj(w) (inverse) as four fused multiply-adds
+template <int DIR, class R>
+__device__ __forceinline__ cx<R> twfma(cx<R> a, cx<R> w, cx<R> c) {
+    const R wy = DIR < 0 ? w.y : -w.y;
+    return {fmad(a.x, w.x, fmad(-a.y, wy, c.x)), fmad(a.x, wy, fmad(a.y, w.x, c.y))};
+}
+// 2 a - s, the partner of s = a + b in a butterfly, by one fused multiply-add per part
+template <class R>
+__device__ __forceinline__ cx<R> twice_minus(cx<R> a, cx<R> s) {
+    return {fmad(R(2), a.x, -s.x), fmad(R(2), a.y, -s.y)};
+}
 
 // ----------------------------------------------------------------- butterflies
 // In-register DFT of length R with sign DIR: v[k] <- sum_j v[j] exp(DIR 2 pi i jk/R).
@@ -101,14 +117,25 @@ struct DFT<5, DIR, T> {
     }
 };
 
+// Radix 8 as three layers of radix-2 butterflies.  The first layer pairs
+// inputs j and j+4 (s = v_j + v_j+4, d = v_j - v_j+4); its variants below fold
+// an input twiddle or an input scale into the butterfly with fused
+// multiply-adds (d is formed as 2 v_j - s), which the layers after it share.
 template <int DIR, class T>
 struct DFT<8, DIR, T> {
-    static __device__ __forceinline__ void run(cx<T>* v) {
+    static __device__ __forceinline__ void finish(const cx<T> (&s)[4], const cx<T> (&d)[4], cx<T>* v) {
         const T q = T(0.70710678118654752440);
-        cx<T> a[4] = {v[0], v[2], v[4], v[6]};
-        cx<T> b[4] = {v[1], v[3], v[5], v[7]};
-        DFT<4, DIR, T>::run(a);
-        DFT<4, DIR, T>::run(b);
+        // radix-4 on the even inputs (0, 2, 4, 6) and on the odd ones (1, 3, 5, 7)
+        cx<T> a[4], b[4];
+        const cx<T> ra = rot<DIR>(d[2]), rb = rot<DIR>(d[3]);
+        a[0] = s[0] + s[2];
+        a[2] = s[0] - s[2];
+        a[1] = d[0] + ra;
+        a[3] = d[0] - ra;
+        b[0] = s[1] + s[3];
+        b[2] = s[1] - s[3];
+        b[1] = d[1] + rb;
+        b[3] = d[1] - rb;
         // b[k] *= exp(DIR 2 pi i k / 8)
         b[1] = {q * (b[1].x - DIR * b[1].y), q * (b[1].y + DIR * b[1].x)};
         b[2] = rot<DIR>(b[2]);
@@ -118,6 +145,37 @@ struct DFT<8, DIR, T> {
             v[k] = a[k] + b[k];
             v[k + 4] = a[k] - b[k];
         }
+    }
+    static __device__ __forceinline__ void run(cx<T>* v) {
+        cx<T> s[4], d[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            s[j] = v[j] + v[j + 4];
+            d[j] = v[j] - v[j + 4];
+        }
+        finish(s, d, v);
+    }
+    // inputs multiplied first by w[j] (forward) or conj(w[j]) (inverse), j = 1..7
+    static __device__ __forceinline__ void run_tw(cx<T>* v, const cx<T>* w) {
+        cx<T> s[4], d[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const cx<T> a = j == 0 ? v[0] : twmul<DIR>(v[j], w[j]);
+            s[j] = twfma<DIR>(v[j + 4], w[j + 4], a);
+            d[j] = twice_minus(a, s[j]);
+        }
+        finish(s, d, v);
+    }
+    // inputs multiplied first by the real k[j], j = 0..7
+    static __device__ __forceinline__ void run_scaled(cx<T>* v, const T* k) {
+        cx<T> s[4], d[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const cx<T> p = scale(v[j + 4], k[j + 4]);
+            s[j] = {fmad(k[j], v[j].x, p.x), fmad(k[j], v[j].y, p.y)};
+            d[j] = {fmad(k[j], v[j].x, -p.x), fmad(k[j], v[j].y, -p.y)};
+        }
+        finish(s, d, v);
     }
 };
 
@@ -334,8 +392,10 @@ struct TeamFFT {
     // exchange serves all of them.  `lds` stores the NC values of one position
     // together (put2/get2 of cx[NC] at position base + off, off a compile-time
     // constant); `tw(m)` returns exp(-2 pi i m / 2N).
+    // ks: if not null, per-element real scales applied to the input of stage 0
     template <int I, int NC, class Lds, class Tw>
-    static __device__ __forceinline__ void stage(cx<Real> (&d)[NC][E], int t, const Tw& tw, Lds& lds) {
+    static __device__ __forceinline__ void stage(cx<Real> (&d)[NC][E], int t, const Tw& tw, Lds& lds,
+                                                 const Real (*ks)[E] = nullptr) {
         if constexpr (I < S) {
             constexpr int R = radix(I);
             constexpr int Ns = span(I);
@@ -367,10 +427,24 @@ struct TeamFFT {
                 for (int c = 0; c < NC; ++c) {
                     cx<Real>* v = d[c] + s * R;
                     if constexpr (Ns > 1) {
+                        if constexpr (R == 8) {
+                            DFT<8, DIR, Real>::run_tw(v, w);
+                        } else {
 #pragma unroll
-                        for (int r = 1; r < R; ++r) v[r] = twmul<DIR>(v[r], w[r]);
+                            for (int r = 1; r < R; ++r) v[r] = twmul<DIR>(v[r], w[r]);
+                            DFT<R, DIR, Real>::run(v);
+                        }
+                    } else if (I == 0 && ks != nullptr) {
+                        if constexpr (R == 8) {
+                            DFT<8, DIR, Real>::run_scaled(v, ks[c] + s * R);
+                        } else {
+#pragma unroll
+                            for (int r = 0; r < R; ++r) v[r] = scale(v[r], ks[c][s * R + r]);
+                            DFT<R, DIR, Real>::run(v);
+                        }
+                    } else {
+                        DFT<R, DIR, Real>::run(v);
                     }
-                    DFT<R, DIR, Real>::run(v);
                 }
             }
             if constexpr (I + 1 < S) {
@@ -422,6 +496,12 @@ struct TeamFFT {
     template <int NC, class Lds, class Tw>
     static __device__ __forceinline__ void run(cx<Real> (&d)[NC][E], int t, const Tw& tw, Lds& lds) {
         stage<0, NC>(d, t, tw, lds);
+    }
+    // the same, with the input of chain c, slot e first multiplied by the real ks[c][e]
+    template <int NC, class Lds, class Tw>
+    static __device__ __forceinline__ void run_scaled(cx<Real> (&d)[NC][E], int t, const Tw& tw, Lds& lds,
+                                                      const Real (&ks)[NC][E]) {
+        stage<0, NC>(d, t, tw, lds, ks);
     }
 
     // single line per thread, twiddles from a global table

@@ -368,7 +368,7 @@ p3_conv(const Batch<DT> bt) {
     auto xoff = [&](int e) { return xl + uint32_t(Ff::in_pos(0, e)) * uint32_t(s0); };
 
     cx<Real> x[E], w[E];
-    Real ke[E], ko[E];
+    Real kk[2][E];  // kernel values of the even and odd outputs
 #pragma unroll
     for (int e = 0; e < E; ++e) {
         x[e] = w2.ld(ub, xoff(e));
@@ -378,8 +378,8 @@ p3_conv(const Batch<DT> bt) {
     for (int e = 0; e < E; ++e) {
         const int m = Ff::out_pos(t, e);
         const int a = 2 * m, b = 2 * m + 1;
-        ke[e] = Real(Kq[kl + uint32_t(a <= N ? a : 2 * N - a) * N]);
-        ko[e] = Real(Kq[kl + uint32_t(b <= N ? b : 2 * N - b) * N]);
+        kk[0][e] = Real(Kq[kl + uint32_t(a <= N ? a : 2 * N - a) * N]);
+        kk[1][e] = Real(Kq[kl + uint32_t(b <= N ? b : 2 * N - b) * N]);
     }
     // Stage twiddles: per-stage rows of both transforms (shared when their
     // radices match) for n >= 512, where the saved index arithmetic outweighs
@@ -403,16 +403,12 @@ p3_conv(const Batch<DT> bt) {
     ChainLds<Real, SEQ> lds{sb, B * SL, int(threadIdx.x % (B * SL))};
     if constexpr (kRows) Ff::template run<2>(d, t, TwRows<Real>{stw}, lds);
     else Ff::template run<2>(d, t, tl, lds);
-#pragma unroll
-    for (int e = 0; e < E; ++e) {
-        d[0][e] = scale(d[0][e], ke[e]);
-        d[1][e] = scale(d[1][e], ko[e]);
-    }
-    if constexpr (kRows) Fi::template run<2>(d, t, TwRows<Real>{rows_i}, lds);
-    else Fi::template run<2>(d, t, tl, lds);
+    // the multiply by K is folded into the first stage of the inverse
+    if constexpr (kRows) Fi::template run_scaled<2>(d, t, TwRows<Real>{rows_i}, lds, kk);
+    else Fi::template run_scaled<2>(d, t, tl, lds, kk);
     if (k2 != 0) {
 #pragma unroll
-        for (int e = 0; e < E; ++e) w2.st(ub, xoff(e), d[0][e] + mul_conj(d[1][e], w[e]));
+        for (int e = 0; e < E; ++e) w2.st(ub, xoff(e), twfma<+1>(d[1][e], w[e], d[0][e]));
     }
 }
 
@@ -526,7 +522,7 @@ p4_inv(const Batch<DT> bt) {
     F::template run<2>(d, t, tl, lds);
 #pragma unroll
     for (int e = 0; e < E; ++e)
-        w1.st(W1I::at(i0, F::out_pos(t, e), k2), d[0][e] + mul_conj(d[1][e], w[e]));
+        w1.st(W1I::at(i0, F::out_pos(t, e), k2), twfma<+1>(d[1][e], w[e], d[0][e]));
 }
 
 // ------------------------------------------------------------------ P5
