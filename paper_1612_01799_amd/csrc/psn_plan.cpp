@@ -209,6 +209,11 @@ struct BatchCache {
     void* arena = nullptr;
     size_t arena_bytes = 0;
     hipStream_t capture = nullptr;
+    // branch streams and fork/join events of the capture: each (n, precision)
+    // group runs on its own branch, so the graph lets small groups overlap
+    std::vector<hipStream_t> branch;
+    std::vector<hipEvent_t> join;
+    hipEvent_t fork = nullptr;
     std::map<std::vector<const void*>, hipGraphExec_t> graphs;
     void clear_graphs() {
         for (auto& g : graphs) (void)hipGraphExecDestroy(g.second);
@@ -472,12 +477,36 @@ psn_status psn_solve_batched(int count, psn_plan* const* plans, const void* cons
         }
         if (!bc.capture && !hip_ok(hipStreamCreateWithFlags(&bc.capture, hipStreamNonBlocking), "hipStreamCreate"))
             return PSN_EDEVICE;
+        if (!bc.fork && !hip_ok(hipEventCreateWithFlags(&bc.fork, hipEventDisableTiming), "hipEventCreate"))
+            return PSN_EDEVICE;
+        const size_t nb = groups.size() - 1;  // the first group stays on the capture stream
+        while (bc.branch.size() < nb) {
+            hipStream_t st = nullptr;
+            hipEvent_t ev = nullptr;
+            if (!hip_ok(hipStreamCreateWithFlags(&st, hipStreamNonBlocking), "hipStreamCreate")) return PSN_EDEVICE;
+            if (!hip_ok(hipEventCreateWithFlags(&ev, hipEventDisableTiming), "hipEventCreate")) {
+                (void)hipStreamDestroy(st);
+                return PSN_EDEVICE;
+            }
+            bc.branch.push_back(st);
+            bc.join.push_back(ev);
+        }
         if (!hip_ok(hipStreamBeginCapture(bc.capture, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture"))
             return PSN_EDEVICE;
-        hipError_t le = hipSuccess;
+        hipError_t le = hipEventRecord(bc.fork, bc.capture);
+        size_t gi = 0;
         for (auto& g : groups) {
-            le = psn_host::launch_group(g.second.data(), int(g.second.size()), bc.capture);
             if (le != hipSuccess) break;
+            if (gi == 0) {
+                le = psn_host::launch_group(g.second.data(), int(g.second.size()), bc.capture);
+            } else {
+                hipStream_t st = bc.branch[gi - 1];
+                le = hipStreamWaitEvent(st, bc.fork, 0);
+                if (le == hipSuccess) le = psn_host::launch_group(g.second.data(), int(g.second.size()), st);
+                if (le == hipSuccess) le = hipEventRecord(bc.join[gi - 1], st);
+                if (le == hipSuccess) le = hipStreamWaitEvent(bc.capture, bc.join[gi - 1], 0);
+            }
+            ++gi;
         }
         hipGraph_t graph = nullptr;
         const hipError_t ee = hipStreamEndCapture(bc.capture, &graph);
