@@ -61,7 +61,15 @@ constexpr int pick_cols_p3_div(int N, int bmax, int cxbytes, int T, int layout_t
     return 1;
 }
 
-constexpr int rows_padded(int N) { return N + (N >> 4) + 1; }
+// LDS row pitch of the contiguous passes (in elements): room for the skew of
+// one slot per 16, rounded to 8 mod 32 so that the rows one wave touches at
+// once (8-byte elements: 4 rows per 256-byte bank sweep; 16-byte: 2 rows)
+// start in different banks
+constexpr int rows_padded(int N) {
+    int np = N + (N >> 4) + 1;
+    while (np % 32 != 8) ++np;
+    return np;
+}
 
 // lines per workgroup of the contiguous passes; their LDS holds the lines and
 // the 2N-entry twiddle table
