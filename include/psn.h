@@ -113,8 +113,15 @@ psn_status psn_solve(psn_plan *p, const void *rho, void *u, void *stream);
 
 /* Enqueue `count` independent solves, possibly of different sizes, as one
  * batch (many densities on one device).  plans[i], rho[i], u[i] as for
- * psn_solve; the same plan may appear more than once (its solves are then
- * ordered on the stream).  Errors: as psn_solve, for the first bad entry. */
+ * psn_solve; the same plan may appear more than once.  Each entry runs in its
+ * own region of a per-device workspace arena (grown on demand, which
+ * synchronises the device; held until the process ends), entries of one
+ * (n, precision) share each kernel launch, and the launch sequence is
+ * captured once per argument list into a HIP graph and replayed.  The arena
+ * is shared by all batched calls on a device, so such calls must not overlap
+ * across streams.  count == 0 does nothing.
+ * Errors: as psn_solve, for the first bad entry; PSN_ENOMEM if the arena
+ * cannot grow. */
 psn_status psn_solve_batched(int count, psn_plan *const *plans,
                              const void *const *rho, void *const *u, void *stream);
 

@@ -641,12 +641,22 @@ struct Sched {
     static constexpr int e8 = elems_per_thread(N, 8), e16 = elems_per_thread(N, 4);
     static constexpr TileV d24{C::BS, C::T24}, d3{C::BP3, C::T3};
     // P2/P4 keep the W2 layout tile (B = BS); P3 tiles must divide it
-    static constexpr TileV v24[3] = {d24, pick_tile(N, {C::BS, N / e16}, d24, C::CX),
-                                     pick_tile(N, {C::BS, C::T24, 1, true}, d24, C::CX)};
-    // P3: one row per workgroup, the row pair k1, M-k1 per workgroup, or one row
-    // with the chains exchanged one at a time
-    static constexpr TileV v3[3] = {d3, pick_tile3(N, {C::BP3, C::T3, 2}, d3, C::CX, C::BS),
-                                    pick_tile3(N, {C::BP3, C::T3, 1, true}, d3, C::CX, C::BS)};
+    // Sizes with a factor 3 or 5 keep all odd factors in every thread, so their
+    // teams are small (8 threads for a 160-point line); their second candidate
+    // halves the elements per thread instead (twice the threads per line, a
+    // longer radix plan).
+    static constexpr int odd = N / (N & -N);
+    static constexpr int eh = odd * 2;
+    static constexpr TileV v24[3] = {
+        d24, pick_tile(N, odd > 1 ? TileV{C::BS, N / eh} : TileV{C::BS, N / e16}, d24, C::CX),
+        pick_tile(N, {C::BS, C::T24, 1, true}, d24, C::CX)};
+    // P3: one row per workgroup; the row pair k1, M-k1 per workgroup (sizes with
+    // an odd factor: half the elements per thread); or one row with the chains
+    // exchanged one at a time
+    static constexpr TileV v3[3] = {
+        d3,
+        pick_tile3(N, odd > 1 ? TileV{C::BP3, N / eh, 1} : TileV{C::BP3, C::T3, 2}, d3, C::CX, C::BS),
+        pick_tile3(N, {C::BP3, C::T3, 1, true}, d3, C::CX, C::BS)};
     static_assert(tile_ok(N, d24, C::CX) && tile_ok(N, d3, C::CX), "default tiles must fit");
 };
 
