@@ -650,6 +650,12 @@ __device__ __forceinline__ void gst(cx<R>* p, cx<R> v) {
     *(PSN_GLOBAL vec2<R>*)(p) = vec2<R>{v.x, v.y};
 }
 __device__ __forceinline__ uint32_t gld(const uint32_t* p) { return *(const PSN_GLOBAL uint32_t*)(p); }
+// two consecutive complex floats in one 16-byte access (p 16-byte aligned)
+typedef float psn_f4 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ void gst2(cx<float>* p, cx<float> a, cx<float> b) {
+    *(PSN_GLOBAL psn_f4*)(p) = psn_f4{a.x, a.y, b.x, b.y};
+}
+
 __device__ __forceinline__ void gst(uint32_t* p, uint32_t v) { *(PSN_GLOBAL uint32_t*)(p) = v; }
 
 // ld/st(i) address element i; ld/st(ub, off) address element ub + off with ub
@@ -662,6 +668,8 @@ struct Work<DT_F32> {
     __device__ __forceinline__ void st(size_t i, cx<float> v) const { gst(p + i, v); }
     __device__ __forceinline__ cx<float> ld(size_t ub, uint32_t off) const { return gld((p + ub) + off); }
     __device__ __forceinline__ void st(size_t ub, uint32_t off, cx<float> v) const { gst((p + ub) + off, v); }
+    // elements i and i+1 (i even)
+    __device__ __forceinline__ void st2(size_t i, cx<float> a, cx<float> b) const { gst2(p + i, a, b); }
 };
 template <>
 struct Work<DT_F64> {
@@ -670,6 +678,10 @@ struct Work<DT_F64> {
     __device__ __forceinline__ void st(size_t i, cx<double> v) const { gst(p + i, v); }
     __device__ __forceinline__ cx<double> ld(size_t ub, uint32_t off) const { return gld((p + ub) + off); }
     __device__ __forceinline__ void st(size_t ub, uint32_t off, cx<double> v) const { gst((p + ub) + off, v); }
+    __device__ __forceinline__ void st2(size_t i, cx<double> a, cx<double> b) const {
+        gst(p + i, a);
+        gst(p + i + 1, b);
+    }
 };
 // FP32 high part + bfloat16 low part (two per 32-bit word): 6 bytes per real.
 template <>
@@ -697,6 +709,11 @@ struct Work<DT_SPLIT> {
         gst((hi + ub) + off, h);
         gst((lo + ub) + off, low_of(v, h));
     }
+    __device__ __forceinline__ void st2(size_t i, cx<double> a, cx<double> b) const {
+        st(i, a);
+        st(i + 1, b);
+    }
+
 };
 
 }  // namespace psn
