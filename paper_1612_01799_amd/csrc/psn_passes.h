@@ -300,30 +300,32 @@ p2_fwd(const Batch<DT> bt) {
     for (int e = 0; e < E; ++e) d[1][e] = d[0][e] * w[e];
     ChainLds<Real, SEQ> lds{sb, B, c};
     F::template run<2>(d, t, tl, lds);
-    if constexpr (!SEQ) {
+    {
         // Stage the workgroup's output in LDS in W2 order (slot-major, B columns
-        // per slot: the 2N B-element exchange area), then store whole runs of
-        // KB * B elements, two consecutive elements per lane.
+        // per slot), then store whole runs of KB * B elements, two consecutive
+        // elements per lane.  The two-chain exchange area holds all 2N slots;
+        // the one-chain area holds N, so that variant stages in two rounds.
         constexpr int KB = WI::KB, RUN = KB * B;
-        __syncthreads();  // the last exchange's reads are done
-#pragma unroll
-        for (int e = 0; e < E; ++e) {
-            const int m = F::out_pos(t, e);
-            sb[WI::slot(2 * m) * B + c] = d[0][e];
-            sb[WI::slot(2 * m + 1) * B + c] = d[1][e];
-        }
-        __syncthreads();
+        constexpr int HALF = SEQ ? N : 2 * N;  // slots per round
+        static_assert((HALF * B) % RUN == 0, "rounds cover whole runs");
         const size_t tile0 = WI::at(i0, 0, tile * B);  // (slot 0, column tile*B): start of block 0's run
-        for (int g = 2 * int(threadIdx.x); g < 2 * N * B; g += 2 * B * TT) {
-            const int b = g / RUN, w = g % RUN;
-            w2.st2(tile0 + size_t(b) * WI::blk + w, sb[g], sb[g + 1]);
-        }
-    } else {
 #pragma unroll
-        for (int e = 0; e < E; ++e) {
-            const int m = F::out_pos(t, e);
-            w2.st(WI::at(i0, 2 * m, k2), d[0][e]);
-            w2.st(WI::at(i0, 2 * m + 1, k2), d[1][e]);
+        for (int h = 0; h < 2 * N / HALF; ++h) {
+            __syncthreads();  // the last exchange's (or round's) reads are done
+#pragma unroll
+            for (int e = 0; e < E; ++e) {
+                const int m = F::out_pos(t, e);
+#pragma unroll
+                for (int ch = 0; ch < 2; ++ch) {
+                    const int sl = WI::slot(2 * m + ch) - h * HALF;
+                    if (sl >= 0 && sl < HALF) sb[sl * B + c] = d[ch][e];
+                }
+            }
+            __syncthreads();
+            for (int g = 2 * int(threadIdx.x); g < HALF * B; g += 2 * B * TT) {
+                const int gg = h * HALF * B + g;
+                w2.st2(tile0 + size_t(gg / RUN) * WI::blk + gg % RUN, sb[g], sb[g + 1]);
+            }
         }
     }
 }
