@@ -42,6 +42,15 @@ struct psn_plan {
 
 namespace psn_host {
 
+// Kernel spectrum layout: planes of (n+1) x n reals per folded k~1, each tiled
+// over k2 as [k2 / KT][k~0][k2 % KT] with KT the largest of 8, 4, 2, 1 dividing
+// n, so the middle pass's workgroup (one k~1, a tile of k2) reads one run.
+__host__ __device__ constexpr int k_tile(int n) { return n % 8 == 0 ? 8 : n % 4 == 0 ? 4 : n % 2 == 0 ? 2 : 1; }
+__host__ __device__ constexpr size_t k_index(int n, int kt1, int kt0, int k2) {
+    return (size_t(kt1) * (n / k_tile(n)) + k2 / k_tile(n)) * size_t(n + 1) * k_tile(n) + size_t(kt0) * k_tile(n) +
+           k2 % k_tile(n);
+}
+
 // k1 block of the W2 layout: the largest power of two <= sqrt(2n) dividing 2n
 constexpr int w2_k1_block(int n) {
     int kb = 1;

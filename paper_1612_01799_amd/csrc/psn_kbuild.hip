@@ -116,18 +116,17 @@ __global__ void k_assemble(const double* __restrict__ A0, const double* __restri
     const double C0 = Cc[0], C2 = Cc[1];
     const double b0 = 2.0 * kPi * kt0 / p0, b1 = 2.0 * kPi * kt1 / p1, b2 = 2.0 * kPi / p2;
     const double q01 = b0 * b0 + b1 * b1;
-    const size_t row = (size_t(kt1) * np1 + kt0) * n;
     for (int k2 = threadIdx.x; k2 <= n; k2 += blockDim.x) {
         double s = 0.0;
         for (int j = 0; j < terms; ++j) s = fma(cj[j], A2[size_t(j) * np1 + k2], s);
         const double v = s + C0 - (C2 / 6.0) * (q01 + b2 * b2 * double(k2) * k2);
         if (k2 == 0) edge[0] = v;
         else if (k2 == n) edge[1] = v;
-        else K[row + k2] = Kt(scale * v);
+        else K[psn_host::k_index(n, kt1, kt0, k2)] = Kt(scale * v);
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-        K[row] = Kt(scale * 0.5 * (edge[0] + edge[1]));
+        K[psn_host::k_index(n, kt1, kt0, 0)] = Kt(scale * 0.5 * (edge[0] + edge[1]));
         Kb[size_t(kt1) * np1 + kt0] = Kt(scale * 0.5 * (edge[0] - edge[1]));
     }
 }

@@ -9,7 +9,7 @@
 //   W2     : n * M * n complex, blocked over k1 and tiled over k2 (W2Index)
 //            so that both the axis-1 passes (fixed i0, all k1) and the axis-0
 //            pass (fixed k1, all i0) read and write long contiguous runs
-//   K      : [k1~][k0~][k2]          (n+1)^2 * n reals, folded k~ = min(k, M-k)
+//   K      : [k1~][k2/KT][k0~][k2%KT] (n+1)^2 * n reals, folded k~ = min(k, M-k)
 //   Kb     : [k1~][k0~]              (n+1)^2 reals
 // The real-to-complex transform along axis 2 gives n+1 frequencies; the two
 // real ones (k2 = 0 and k2 = n) travel packed as one complex value in column
@@ -393,8 +393,11 @@ p3_conv(const Batch<DT> bt) {
                   "lane offsets fit 32 bits");
     const size_t ub = WI::at(0, q, tile * B);
     const uint32_t xl = uint32_t(c) + uint32_t(set) * Cfg<N, DT>::BS + uint32_t(t) * uint32_t(s0);
-    const typename C::Kt* Kq = K + (size_t(q) * (N + 1) * N + size_t(tile) * B);
-    const uint32_t kl = uint32_t(c) + ((set != 0 && q == 0) ? uint32_t(N) * (N + 1) * N : 0u);
+    // kernel row of this lane's column in the tiled K layout (plane q, or n for
+    // the set-1 row of pair 0); the folded k0 then steps by the K tile width
+    constexpr uint32_t KT = uint32_t(psn_host::k_tile(N));
+    const typename C::Kt* Kq = K;
+    const uint32_t kl = uint32_t(psn_host::k_index(N, (set != 0 && q == 0) ? N : q, 0, k2));
     auto xoff = [&](int e) { return xl + uint32_t(Ff::in_pos(0, e)) * uint32_t(s0); };
 
     cx<Real> x[E], w[E];
@@ -408,8 +411,8 @@ p3_conv(const Batch<DT> bt) {
     for (int e = 0; e < E; ++e) {
         const int m = Ff::out_pos(t, e);
         const int a = 2 * m, b = 2 * m + 1;
-        kk[0][e] = Real(Kq[kl + uint32_t(a <= N ? a : 2 * N - a) * N]);
-        kk[1][e] = Real(Kq[kl + uint32_t(b <= N ? b : 2 * N - b) * N]);
+        kk[0][e] = Real(Kq[kl + uint32_t(a <= N ? a : 2 * N - a) * KT]);
+        kk[1][e] = Real(Kq[kl + uint32_t(b <= N ? b : 2 * N - b) * KT]);
     }
     // Stage twiddles: per-stage rows of both transforms (shared when their
     // radices match) for n >= 512, where the saved index arithmetic outweighs
@@ -472,7 +475,7 @@ p3_col0(const Batch<DT> bt) {
     const int kt1 = (q == 0) ? (set ? N : 0) : q;
     const int partner = (q == 0) ? set : 1 - set;
     const size_t base = WI::at(0, k1, 0);
-    const typename C::Kt* Krow = K + size_t(kt1) * (N + 1) * N;
+    const typename C::Kt* Krow = K + psn_host::k_index(N, kt1, 0, 0);  // column 0 of plane kt1
     const typename C::Kt* Kbr = Kb + size_t(kt1) * (N + 1);
 
     cx<Real> x[Ff::E], acc[Ff::E];
@@ -496,7 +499,7 @@ p3_col0(const Batch<DT> bt) {
             const int kt0 = k0 <= N ? k0 : 2 * N - k0;
             const int mp = p == 0 ? (m == 0 ? 0 : N - m) : N - 1 - m;
             const cx<Real> zp = conj(sb[partner * N + mp]);
-            d[e] = scale(d[e], Real(Krow[size_t(kt0) * N])) + scale(zp, Real(Kbr[kt0]));
+            d[e] = scale(d[e], Real(Krow[size_t(kt0) * psn_host::k_tile(N)])) + scale(zp, Real(Kbr[kt0]));
         }
         Fi::run(d, t, tw, lds);
 #pragma unroll

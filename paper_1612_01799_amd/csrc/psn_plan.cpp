@@ -599,12 +599,11 @@ psn_status psn_kernel_download(const psn_plan* p, double* octant) {
     const double M = 2.0 * n, inv = M * M * M;
     for (size_t a = 0; a < np1; ++a)
         for (size_t b = 0; b < np1; ++b) {
-            const size_t row = (b * np1 + a) * n;  // stored [k1][k0][k2]
             double* dst = octant + (a * np1 + b) * np1;
-            const double al = get(hk, row), be = get(hb, b * np1 + a);
+            const double al = get(hk, psn_host::k_index(int(n), int(b), int(a), 0)), be = get(hb, b * np1 + a);
             dst[0] = (al + be) * inv;
             dst[n] = (al - be) * inv;
-            for (size_t c = 1; c < n; ++c) dst[c] = get(hk, row + c) * inv;
+            for (size_t c = 1; c < n; ++c) dst[c] = get(hk, psn_host::k_index(int(n), int(b), int(a), int(c))) * inv;
         }
     return PSN_OK;
 }
