@@ -650,6 +650,8 @@ __device__ __forceinline__ void gst(cx<R>* p, cx<R> v) {
     *(PSN_GLOBAL vec2<R>*)(p) = vec2<R>{v.x, v.y};
 }
 __device__ __forceinline__ uint32_t gld(const uint32_t* p) { return *(const PSN_GLOBAL uint32_t*)(p); }
+__device__ __forceinline__ float gld(const float* p) { return *(const PSN_GLOBAL float*)(p); }
+__device__ __forceinline__ double gld(const double* p) { return *(const PSN_GLOBAL double*)(p); }
 // two consecutive complex floats in one 16-byte access (p 16-byte aligned)
 typedef float psn_f4 __attribute__((ext_vector_type(4)));
 __device__ __forceinline__ void gst2(cx<float>* p, cx<float> a, cx<float> b) {
@@ -658,16 +660,38 @@ __device__ __forceinline__ void gst2(cx<float>* p, cx<float> a, cx<float> b) {
 
 __device__ __forceinline__ void gst(uint32_t* p, uint32_t v) { *(PSN_GLOBAL uint32_t*)(p) = v; }
 
+// Pointer `base` advanced by `ob` bytes.  With base uniform over the wave and
+// ob a 32-bit lane value, the access takes the scalar-base form: the uniform
+// part stays in scalar registers and the lane part is one 32-bit register.
+// `p` kept in scalar registers as an opaque value, so that the compiler does
+// not move a uniform offset added to it into per-lane 64-bit address
+// arithmetic.  p must be uniform over the wave.
+template <class T>
+__device__ __forceinline__ T* sbase(T* p) {
+    asm("" : "+s"(p));
+    return p;
+}
+template <class T>
+__device__ __forceinline__ T* byte_off(T* base, uint32_t ob) {
+    return reinterpret_cast<T*>(reinterpret_cast<char*>(base) + ob);
+}
+template <class T>
+__device__ __forceinline__ const T* byte_off(const T* base, uint32_t ob) {
+    return reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + ob);
+}
+
 // ld/st(i) address element i; ld/st(ub, off) address element ub + off with ub
-// uniform over the wave and off a 32-bit lane offset, which keeps the lane
-// part of the address in one 32-bit register.
+// uniform over the wave and off a 32-bit lane offset whose byte offset also
+// fits 32 bits.
 template <>
 struct Work<DT_F32> {
     cx<float>* p;
     __device__ __forceinline__ cx<float> ld(size_t i) const { return gld(p + i); }
     __device__ __forceinline__ void st(size_t i, cx<float> v) const { gst(p + i, v); }
-    __device__ __forceinline__ cx<float> ld(size_t ub, uint32_t off) const { return gld((p + ub) + off); }
-    __device__ __forceinline__ void st(size_t ub, uint32_t off, cx<float> v) const { gst((p + ub) + off, v); }
+    __device__ __forceinline__ cx<float> ld(size_t ub, uint32_t off) const { return gld(byte_off(sbase(p + ub), off * 8u)); }
+    __device__ __forceinline__ void st(size_t ub, uint32_t off, cx<float> v) const {
+        gst(byte_off(sbase(p + ub), off * 8u), v);
+    }
     // elements i and i+1 (i even)
     __device__ __forceinline__ void st2(size_t i, cx<float> a, cx<float> b) const { gst2(p + i, a, b); }
 };
@@ -676,8 +700,12 @@ struct Work<DT_F64> {
     cx<double>* p;
     __device__ __forceinline__ cx<double> ld(size_t i) const { return gld(p + i); }
     __device__ __forceinline__ void st(size_t i, cx<double> v) const { gst(p + i, v); }
-    __device__ __forceinline__ cx<double> ld(size_t ub, uint32_t off) const { return gld((p + ub) + off); }
-    __device__ __forceinline__ void st(size_t ub, uint32_t off, cx<double> v) const { gst((p + ub) + off, v); }
+    __device__ __forceinline__ cx<double> ld(size_t ub, uint32_t off) const {
+        return gld(byte_off(sbase(p + ub), off * 16u));
+    }
+    __device__ __forceinline__ void st(size_t ub, uint32_t off, cx<double> v) const {
+        gst(byte_off(sbase(p + ub), off * 16u), v);
+    }
     __device__ __forceinline__ void st2(size_t i, cx<double> a, cx<double> b) const {
         gst(p + i, a);
         gst(p + i + 1, b);
@@ -702,12 +730,12 @@ struct Work<DT_SPLIT> {
         gst(lo + i, low_of(v, h));
     }
     __device__ __forceinline__ cx<double> ld(size_t ub, uint32_t off) const {
-        return join(gld((hi + ub) + off), gld((lo + ub) + off));
+        return join(gld(byte_off(sbase(hi + ub), off * 8u)), gld(byte_off(sbase(lo + ub), off * 4u)));
     }
     __device__ __forceinline__ void st(size_t ub, uint32_t off, cx<double> v) const {
         const cx<float> h{float(v.x), float(v.y)};
-        gst((hi + ub) + off, h);
-        gst((lo + ub) + off, low_of(v, h));
+        gst(byte_off(sbase(hi + ub), off * 8u), h);
+        gst(byte_off(sbase(lo + ub), off * 4u), low_of(v, h));
     }
     __device__ __forceinline__ void st2(size_t i, cx<double> a, cx<double> b) const {
         st(i, a);

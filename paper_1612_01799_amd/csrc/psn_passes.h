@@ -348,8 +348,18 @@ struct P3Rows {
     static constexpr bool value = N >= 512;
 };
 
+// Minimum waves per SIMD asked of the compiler for P3: the one-chain variant
+// uses little LDS, so with up to 8 elements per thread it asks for enough
+// waves for three workgroups per CU (FP32 keeps few values live across the
+// forward transform; see kLean).  Longer plans are left unbounded, where a
+// bound would only force spills.
+constexpr int p3_waves(int e, int threads, bool f32, bool seq) {
+    if (!seq || e > 8) return 1;
+    return f32 && threads > 256 ? 6 : 3;
+}
+
 template <int N, int DT, int B, int TT, int SL, bool SEQ>
-__global__ void __launch_bounds__((B * TT * SL), (SEQ ? 3 : 1))
+__global__ void __launch_bounds__((B * TT * SL), (p3_waves(N / TT, B * TT * SL, DT == DT_F32, SEQ)))
 p3_conv(const Batch<DT> bt) {
     using C = Cfg<N, DT>;
     using Real = typename C::Real;
@@ -389,31 +399,51 @@ p3_conv(const Batch<DT> bt) {
     // Addresses: a base uniform over the workgroup (row q, column tile * B)
     // plus a 32-bit lane offset.  Row M-q sits BS elements after row q in the
     // W2 layout; its kernel row is q as well, except for the pair (0, n).
-    static_assert(WI::s0 * N < (size_t(1) << 32) && size_t(N + 1) * (N + 1) * N < (size_t(1) << 32),
-                  "lane offsets fit 32 bits");
+    static_assert(WI::s0 * N * sizeof(cx<double>) < (size_t(1) << 32) &&
+                      size_t(N + 1) * (N + 1) * N * sizeof(double) < (size_t(1) << 32),
+                  "lane byte offsets fit 32 bits");
     const size_t ub = WI::at(0, q, tile * B);
+    // element e sits at the uniform base xb(e) plus the lane offset xl
     const uint32_t xl = uint32_t(c) + uint32_t(set) * Cfg<N, DT>::BS + uint32_t(t) * uint32_t(s0);
-    // kernel row of this lane's column in the tiled K layout (plane q, or n for
-    // the set-1 row of pair 0); the folded k0 then steps by the K tile width
-    constexpr uint32_t KT = uint32_t(psn_host::k_tile(N));
-    const typename C::Kt* Kq = K;
+    auto xb = [&](int e) { return ub + size_t(Ff::in_pos(0, e)) * s0; };
+    // Kernel values of the even and odd outputs a = 2m, b = 2m + 1 of
+    // m = out_pos(t, e) = t + m0(e), at the folded index min(a, 2N - a) of
+    // this lane's kernel row (plane q, or n for the set-1 row of pair 0) in the
+    // tiled K layout, where the folded k0 steps by the K tile width KT.  When a
+    // whole element lies on one side of n, the folded index is a constant plus
+    // 2t or minus 2t: a uniform base plus one of two lane offsets.
+    constexpr int KT = psn_host::k_tile(N);
+    const typename C::Kt* __restrict__ Kq = K;
     const uint32_t kl = uint32_t(psn_host::k_index(N, (set != 0 && q == 0) ? N : q, 0, k2));
-    auto xoff = [&](int e) { return xl + uint32_t(Ff::in_pos(0, e)) * uint32_t(s0); };
+    const uint32_t kup = (kl + uint32_t(2 * t * KT)) * uint32_t(sizeof(typename C::Kt));
+    const uint32_t kdn = (kl + uint32_t(2 * (TT - 1 - t) * KT)) * uint32_t(sizeof(typename C::Kt));
+    auto kval = [&](int e, int odd) -> Real {
+        const int m0 = Ff::out_pos(0, e);
+        if (2 * m0 + 2 * TT - 1 <= N) return Real(gld(byte_off(sbase(Kq + (2 * m0 + odd) * KT), kup)));
+        if (2 * m0 >= N) return Real(gld(byte_off(sbase(Kq + (2 * N - 2 * m0 - odd - 2 * (TT - 1)) * KT), kdn)));
+        const int a = 2 * (m0 + t) + odd;
+        return Real(gld(Kq + kl + uint32_t(a <= N ? a : 2 * N - a) * KT));
+    };
 
     cx<Real> x[E], w[E];
-    Real kk[2][E];  // kernel values of the even and odd outputs
+    Real kk[2][E];
 #pragma unroll
     for (int e = 0; e < E; ++e) {
-        x[e] = w2.ld(ub, xoff(e));
+        x[e] = w2.ld(xb(e), xl);
         w[e] = tw[Ff::in_pos(t, e)];
     }
+    // The one-chain variant keeps fewer values live across the forward
+    // transform (more waves fit): it loads the kernel values after it and
+    // reloads the twiddles w at the end.
+    constexpr bool kLean = SEQ && DT == DT_F32;
+    auto load_k = [&]() {
 #pragma unroll
-    for (int e = 0; e < E; ++e) {
-        const int m = Ff::out_pos(t, e);
-        const int a = 2 * m, b = 2 * m + 1;
-        kk[0][e] = Real(Kq[kl + uint32_t(a <= N ? a : 2 * N - a) * KT]);
-        kk[1][e] = Real(Kq[kl + uint32_t(b <= N ? b : 2 * N - b) * KT]);
-    }
+        for (int e = 0; e < E; ++e) {
+            kk[0][e] = kval(e, 0);
+            kk[1][e] = kval(e, 1);
+        }
+    };
+    if constexpr (!kLean) load_k();
     // Stage twiddles: per-stage rows of both transforms (shared when their
     // radices match) for n >= 512, where the saved index arithmetic outweighs
     // the scattered reads that fill them; else the swizzled 2N-entry table.
@@ -436,12 +466,17 @@ p3_conv(const Batch<DT> bt) {
     ChainLds<Real, SEQ> lds{sb, B * SL, int(threadIdx.x % (B * SL))};
     if constexpr (kRows) Ff::template run<2>(d, t, TwRows<Real>{stw}, lds);
     else Ff::template run<2>(d, t, tl, lds);
+    if constexpr (kLean) load_k();
     // the multiply by K is folded into the first stage of the inverse
     if constexpr (kRows) Fi::template run_scaled<2>(d, t, TwRows<Real>{rows_i}, lds, kk);
     else Fi::template run_scaled<2>(d, t, tl, lds, kk);
+    if constexpr (kLean) {
+#pragma unroll
+        for (int e = 0; e < E; ++e) w[e] = gld(byte_off(sbase(tw + Ff::in_pos(0, e)), uint32_t(t) * uint32_t(C::CX)));
+    }
     if (k2 != 0) {
 #pragma unroll
-        for (int e = 0; e < E; ++e) w2.st(ub, xoff(e), twfma<+1>(d[1][e], w[e], d[0][e]));
+        for (int e = 0; e < E; ++e) w2.st(xb(e), xl, twfma<+1>(d[1][e], w[e], d[0][e]));
     }
 }
 
