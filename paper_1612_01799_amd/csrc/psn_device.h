@@ -117,6 +117,51 @@ struct DFT<5, DIR, T> {
     }
 };
 
+// Lengths R1 * R2 with coprime R1 (a power of two) and R2 (odd), by the
+// prime-factor (Good-Thomas) mapping: input n = (R2 n1 + R1 n2) mod R and
+// output k = (R2 t1 k1 + R1 t2 k2) mod R, with t1 R2 = 1 (mod R1) and
+// t2 R1 = 1 (mod R2), turn exp(2 pi i nk / R) into the product of
+// exp(2 pi i n1 k1 / R1) and exp(2 pi i n2 k2 / R2).  So the DFT is R2 DFTs
+// of length R1 followed by R1 DFTs of length R2, with no twiddle factors
+// between them; both index maps are compile-time register renamings.
+constexpr int mod_inverse(int a, int m) {
+    for (int x = 1; x < m; ++x)
+        if ((a * x) % m == 1) return x;
+    return 1;
+}
+template <int R1, int R2, int DIR, class T>
+struct PrimeFactorDFT {
+    static constexpr int R = R1 * R2;
+    static constexpr int t1 = mod_inverse(R2 % R1, R1), t2 = mod_inverse(R1 % R2, R2);
+    static_assert((R2 * t1) % R1 == 1 % R1 && (R1 * t2) % R2 == 1, "coprime factors");
+    static __device__ __forceinline__ void run(cx<T>* v) {
+        cx<T> a[R2][R1];
+#pragma unroll
+        for (int n2 = 0; n2 < R2; ++n2) {
+#pragma unroll
+            for (int n1 = 0; n1 < R1; ++n1) a[n2][n1] = v[(R2 * n1 + R1 * n2) % R];
+            DFT<R1, DIR, T>::run(a[n2]);
+        }
+#pragma unroll
+        for (int k1 = 0; k1 < R1; ++k1) {
+            cx<T> b[R2];
+#pragma unroll
+            for (int n2 = 0; n2 < R2; ++n2) b[n2] = a[n2][k1];
+            DFT<R2, DIR, T>::run(b);
+#pragma unroll
+            for (int k2 = 0; k2 < R2; ++k2) v[(R2 * t1 * k1 + R1 * t2 * k2) % R] = b[k2];
+        }
+    }
+};
+template <int DIR, class T>
+struct DFT<6, DIR, T> : PrimeFactorDFT<2, 3, DIR, T> {};
+template <int DIR, class T>
+struct DFT<10, DIR, T> : PrimeFactorDFT<2, 5, DIR, T> {};
+template <int DIR, class T>
+struct DFT<12, DIR, T> : PrimeFactorDFT<4, 3, DIR, T> {};
+template <int DIR, class T>
+struct DFT<20, DIR, T> : PrimeFactorDFT<4, 5, DIR, T> {};
+
 // Radix 8 as three layers of radix-2 butterflies.  The first layer pairs
 // inputs j and j+4 (s = v_j + v_j+4, d = v_j - v_j+4); its variants below fold
 // an input twiddle or an input scale into the butterfly with fused
@@ -220,23 +265,28 @@ struct RadixPlan {
 };
 
 // Stages for a length-N transform with E elements per thread: odd radices
-// first, then the largest power-of-two radix (<= 16) dividing both what is
-// left of N and the power-of-two part of E, so each stage gives every thread
-// a whole number of butterflies.
+// first, each merged with a factor 4 or 2 into one prime-factor radix (20, 12,
+// 10, 6) where that divides both what is left of N and E; then the largest
+// power-of-two radix (<= 16) dividing both what is left of N and the
+// power-of-two part of E, so each stage gives every thread a whole number of
+// butterflies.
+constexpr int odd_radix(int f, int rem, int E) {
+    for (int p = 4; p >= 1; p /= 2)
+        if (rem % (f * p) == 0 && E % (f * p) == 0) return f * p;
+    return -1;
+}
 constexpr RadixPlan make_plan(int N, int E) {
     RadixPlan p{0, {}};
     if (N < 1 || E < 1 || N % E != 0) return RadixPlan{-1, {}};
     int rem = N;
     // every radix must divide E: a thread runs E / R butterflies of radix R per stage
-    while (rem % 5 == 0) {
-        if (E % 5 != 0) return RadixPlan{-1, {}};
-        p.r[p.n++] = 5;
-        rem /= 5;
-    }
-    while (rem % 3 == 0) {
-        if (E % 3 != 0) return RadixPlan{-1, {}};
-        p.r[p.n++] = 3;
-        rem /= 3;
+    for (int f = 5; f >= 3; f -= 2) {
+        while (rem % f == 0) {
+            const int R = odd_radix(f, rem, E);
+            if (R < 0) return RadixPlan{-1, {}};
+            p.r[p.n++] = R;
+            rem /= R;
+        }
     }
     int e2 = E & -E;
     while (rem > 1) {

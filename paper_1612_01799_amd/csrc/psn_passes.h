@@ -262,7 +262,7 @@ template <class Real, bool SEQ>
 using ChainLds = std::conditional_t<SEQ, LdsColsSeq<Real>, LdsCols2<Real>>;
 
 template <int N, int DT, int B, int TT, bool SEQ>
-__global__ void __launch_bounds__((B * TT), (SEQ ? 3 : 1))
+__global__ void __launch_bounds__((B * TT), (SEQ && N / TT <= 8 ? 3 : 1))
 p2_fwd(const Batch<DT> bt) {
     using C = Cfg<N, DT>;
     using Real = typename C::Real;
@@ -435,7 +435,7 @@ p3_conv(const Batch<DT> bt) {
     // The one-chain variant keeps fewer values live across the forward
     // transform (more waves fit): it loads the kernel values after it and
     // reloads the twiddles w at the end.
-    constexpr bool kLean = SEQ && DT == DT_F32;
+    constexpr bool kLean = DT == DT_F32 && (SEQ || E > 8);
     auto load_k = [&]() {
 #pragma unroll
         for (int e = 0; e < E; ++e) {
@@ -551,7 +551,7 @@ p3_col0(const Batch<DT> bt) {
 // Unit = (i0, tile of B columns k2).  The even and odd rows of a line are
 // inverted in lockstep and combined as y = y_even + w^-j y_odd.
 template <int N, int DT, int B, int TT, bool SEQ>
-__global__ void __launch_bounds__((B * TT), (SEQ ? 3 : 1))
+__global__ void __launch_bounds__((B * TT), (SEQ && N / TT <= 8 ? 3 : 1))
 p4_inv(const Batch<DT> bt) {
     using C = Cfg<N, DT>;
     using Real = typename C::Real;

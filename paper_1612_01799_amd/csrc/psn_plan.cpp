@@ -2,6 +2,7 @@
 // self-check), device state, and the entry points declared in psn.h.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
@@ -173,6 +174,17 @@ size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
 
 // workspace bytes of one solve: W1 (n^3 complex), W2 (2 n^3 complex), and the
 // low parts of the split format
+// HBM bytes one solve must move: five passes, each one read and one write of
+// its arrays (io: rho and u, s: complex intermediates per real, k: kernel
+// spectrum per real)
+double algorithmic_bytes(const psn_plan* p) {
+    const double n3 = double(p->n) * p->n * p->n, np1 = p->n + 1.0;
+    const double bio = p->dtype == PSN_F32 ? 4 : 8;
+    const double bs = p->dtype == PSN_F32 ? 4 : (p->dtype == PSN_F64 ? 8 : 6);
+    const double bk = p->dtype == PSN_F32 ? 4 : 8;
+    return 2 * bio * n3 + 24 * bs * n3 + bk * np1 * np1 * np1;
+}
+
 size_t slot_bytes(const psn_plan* p) {
     const size_t n3 = size_t(p->n) * p->n * p->n;
     const size_t wb = p->dtype == PSN_SPLIT ? 8 : psn_host::elem_bytes(p->dtype);
@@ -209,8 +221,9 @@ struct BatchCache {
     void* arena = nullptr;
     size_t arena_bytes = 0;
     hipStream_t capture = nullptr;
-    // branch streams and fork/join events of the capture: each (n, precision)
-    // group runs on its own branch, so the graph lets small groups overlap
+    // branch streams and fork/join events of the capture: the (n, precision)
+    // groups are spread over at most kBatchChains parallel chains, so the graph
+    // lets small groups overlap large ones
     std::vector<hipStream_t> branch;
     std::vector<hipEvent_t> join;
     hipEvent_t fork = nullptr;
@@ -222,6 +235,10 @@ struct BatchCache {
 };
 std::mutex g_batch_mutex;
 std::map<int, BatchCache> g_batch;
+// Parallel chains of a batch graph: the number of hardware queues a process
+// gets by default.  A graph with more independent branches than queues runs
+// some of them back to back, in an order the runtime picks.
+constexpr size_t kBatchChains = 4;
 
 }  // namespace
 
@@ -475,11 +492,27 @@ psn_status psn_solve_batched(int count, psn_plan* const* plans, const void* cons
             const psn_plan* p = plans[i];
             groups[{p->n, p->dtype}].push_back(arena_slot(p, rho[i], u[i], static_cast<char*>(bc.arena) + off[i]));
         }
+        // Chains: groups in decreasing order of HBM bytes, each appended to the
+        // chain with the fewest bytes so far (longest-first list scheduling),
+        // so the largest group starts at once and small ones share a chain.
+        std::vector<std::pair<double, const std::vector<psn_host::Slot>*>> order;
+        for (auto& g : groups)
+            order.push_back({algorithmic_bytes(g.second.front().plan) * double(g.second.size()), &g.second});
+        std::stable_sort(order.begin(), order.end(),
+                         [](const auto& a, const auto& b) { return a.first > b.first; });
+        const size_t nchain = std::min(order.size(), kBatchChains);
+        std::vector<std::vector<const std::vector<psn_host::Slot>*>> chains(nchain);
+        std::vector<double> load(nchain, 0.0);
+        for (auto& o : order) {
+            const size_t c = size_t(std::min_element(load.begin(), load.end()) - load.begin());
+            chains[c].push_back(o.second);
+            load[c] += o.first;
+        }
         if (!bc.capture && !hip_ok(hipStreamCreateWithFlags(&bc.capture, hipStreamNonBlocking), "hipStreamCreate"))
             return PSN_EDEVICE;
         if (!bc.fork && !hip_ok(hipEventCreateWithFlags(&bc.fork, hipEventDisableTiming), "hipEventCreate"))
             return PSN_EDEVICE;
-        const size_t nb = groups.size() - 1;  // the first group stays on the capture stream
+        const size_t nb = nchain - 1;  // the first chain stays on the capture stream
         while (bc.branch.size() < nb) {
             hipStream_t st = nullptr;
             hipEvent_t ev = nullptr;
@@ -494,19 +527,19 @@ psn_status psn_solve_batched(int count, psn_plan* const* plans, const void* cons
         if (!hip_ok(hipStreamBeginCapture(bc.capture, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture"))
             return PSN_EDEVICE;
         hipError_t le = hipEventRecord(bc.fork, bc.capture);
-        size_t gi = 0;
-        for (auto& g : groups) {
-            if (le != hipSuccess) break;
-            if (gi == 0) {
-                le = psn_host::launch_group(g.second.data(), int(g.second.size()), bc.capture);
-            } else {
-                hipStream_t st = bc.branch[gi - 1];
-                le = hipStreamWaitEvent(st, bc.fork, 0);
-                if (le == hipSuccess) le = psn_host::launch_group(g.second.data(), int(g.second.size()), st);
-                if (le == hipSuccess) le = hipEventRecord(bc.join[gi - 1], st);
-                if (le == hipSuccess) le = hipStreamWaitEvent(bc.capture, bc.join[gi - 1], 0);
+        // chains 1.. fork from the capture stream first, so that every chain
+        // starts at the head of the graph
+        for (size_t ci = 1; ci < nchain && le == hipSuccess; ++ci) le = hipStreamWaitEvent(bc.branch[ci - 1], bc.fork, 0);
+        for (size_t ci = 0; ci < nchain && le == hipSuccess; ++ci) {
+            hipStream_t st = ci == 0 ? bc.capture : bc.branch[ci - 1];
+            for (const auto* g : chains[ci]) {
+                if (le != hipSuccess) break;
+                le = psn_host::launch_group(g->data(), int(g->size()), st);
             }
-            ++gi;
+        }
+        for (size_t ci = 1; ci < nchain && le == hipSuccess; ++ci) {
+            le = hipEventRecord(bc.join[ci - 1], bc.branch[ci - 1]);
+            if (le == hipSuccess) le = hipStreamWaitEvent(bc.capture, bc.join[ci - 1], 0);
         }
         hipGraph_t graph = nullptr;
         const hipError_t ee = hipStreamEndCapture(bc.capture, &graph);
@@ -553,13 +586,7 @@ psn_status psn_plan_query(const psn_plan* p, psn_plan_info* info) {
     info->C2 = p->C2;
     info->built = p->built ? 1 : 0;
     info->device_bytes = p->device_bytes;
-    // five passes, each one read and one write of its arrays (io: rho and u,
-    // s: complex intermediates per real, k: kernel spectrum per real)
-    const double n3 = double(p->n) * p->n * p->n, np1 = p->n + 1.0;
-    const double bio = p->dtype == PSN_F32 ? 4 : 8;
-    const double bs = p->dtype == PSN_F32 ? 4 : (p->dtype == PSN_F64 ? 8 : 6);
-    const double bk = p->dtype == PSN_F32 ? 4 : 8;
-    info->algorithmic_bytes = 2 * bio * n3 + 24 * bs * n3 + bk * np1 * np1 * np1;
+    info->algorithmic_bytes = algorithmic_bytes(p);
     return PSN_OK;
 }
 

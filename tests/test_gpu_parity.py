@@ -16,7 +16,7 @@ from gpu_common import TOL, gpu_solve, max_rel, oracle_octant, oracle_symbol, to
 pytestmark = pytest.mark.gpu
 psn = pytest.importorskip("paper_1612_01799_amd")
 
-SIZES = [8, 12, 16, 24, 32, 48, 64, 96, 128, 160]
+SIZES = [8, 12, 16, 24, 32, 48, 64, 96, 128, 160, 192, 320, 384]
 
 
 def _mix(n, L, seed):
