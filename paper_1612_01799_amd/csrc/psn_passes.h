@@ -483,29 +483,42 @@ p3_conv(const Batch<DT> bt) {
 // Column 0 of W2 carries Z = A + iB with A, B the spectra of the real k2 = 0
 // and k2 = n planes.  With the partner row -k the product is
 // Z' = a Z(k) + b conj(Z(-k)), a = (K0+Kn)/2 (stored in K's column 0) and
-// b = (K0-Kn)/2 (stored in Kb).  One workgroup holds rows q and M-q (row 0
-// pairs with itself, as does row n).
+// b = (K0-Kn)/2 (stored in Kb).  A row pair is rows q and M-q (row 0 pairs
+// with itself, as does row n); a workgroup holds col0_pairs(N) row pairs so
+// that short lines still fill a 64-lane wave.
 template <int N, int DT>
-__global__ void __launch_bounds__((2 * Cfg<N, DT>::T))
+struct Col0 {
+    static constexpr int T = Cfg<N, DT>::T;
+    static constexpr int G = 2 * T >= 64 ? 1 : (64 / (2 * T) < N ? 64 / (2 * T) : N);  // row pairs per workgroup
+    static constexpr int groups = (N + G - 1) / G;                                    // workgroups per problem
+    static constexpr size_t lds = size_t(G) * 2 * N * Cfg<N, DT>::CX;
+};
+
+template <int N, int DT>
+__global__ void __launch_bounds__((2 * Cfg<N, DT>::T * Col0<N, DT>::G))
 p3_col0(const Batch<DT> bt) {
     using C = Cfg<N, DT>;
     using Real = typename C::Real;
     using Ff = TeamFFT<N, C::T, Real, -1, false>;
     using Fi = TeamFFT<N, C::T, Real, +1, true>;
     using WI = W2Index<N, Cfg<N, DT>::BS>;
+    using G0 = Col0<N, DT>;
     constexpr size_t s0 = WI::s0;
     extern __shared__ __align__(16) unsigned char smem[];
-    cx<Real>* sb = reinterpret_cast<cx<Real>*>(smem);
 
-    if (int(blockIdx.x) >= bt.count * N) return;
-    const Prob<DT>& P = bt.p[blockIdx.x / N];
+    if (int(blockIdx.x) >= bt.count * G0::groups) return;
+    const Prob<DT>& P = bt.p[blockIdx.x / G0::groups];
     const Work<DT>& w2 = P.w2;
     const typename C::Kt* __restrict__ K = P.K;
     const typename C::Kt* __restrict__ Kb = P.Kb;
     const cx<Real>* __restrict__ tw = P.tw;
+    const int g = threadIdx.x / (2 * C::T);  // row pair within the workgroup
     const int set = threadIdx.x & 1;
-    const int t = threadIdx.x >> 1;
-    const int q = blockIdx.x % N;
+    const int t = (threadIdx.x >> 1) % C::T;
+    const int qg = (blockIdx.x % G0::groups) * G0::G + g;
+    const bool live = qg < N;  // the last workgroup may hold pairs past the end
+    const int q = live ? qg : N - 1;
+    cx<Real>* sb = reinterpret_cast<cx<Real>*>(smem) + size_t(g) * 2 * N;
     const int k1 = set == 0 ? q : (q == 0 ? N : 2 * N - q);
     const int kt1 = (q == 0) ? (set ? N : 0) : q;
     const int partner = (q == 0) ? set : 1 - set;
@@ -543,8 +556,10 @@ p3_col0(const Batch<DT> bt) {
             else acc[e] = acc[e] + mul_conj(d[e], tw[Fi::out_pos(t, e)]);
         }
     }
+    if (live) {
 #pragma unroll
-    for (int e = 0; e < Ff::E; ++e) w2.st(base + size_t(Fi::out_pos(t, e)) * s0, acc[e]);
+        for (int e = 0; e < Ff::E; ++e) w2.st(base + size_t(Fi::out_pos(t, e)) * s0, acc[e]);
+    }
 }
 
 // ------------------------------------------------------------------ P4
@@ -794,7 +809,6 @@ hipError_t solve_n(const Batch<DT>& bt, hipStream_t s, hipEvent_t* ev, int v24, 
     using C = Cfg<N, DT>;
     constexpr size_t tws = TwLds<typename C::Real>::slots(N);
     const size_t lds_rows = (size_t(C::LC) * C::NP + tws) * C::CX;
-    const size_t lds_c0 = size_t(2) * N * C::CX;
     const long cnt = bt.count;
     auto mark = [&](int i) {
         if (ev) (void)hipEventRecord(ev[i], s);
@@ -806,7 +820,8 @@ hipError_t solve_n(const Batch<DT>& bt, hipStream_t s, hipEvent_t* ev, int v24, 
     if ((e = launch_p24<N, DT>(bt, s, v24, true)) != hipSuccess) return e;
     mark(2);
     if ((e = launch_p3v<N, DT>(bt, s, v3)) != hipSuccess) return e;
-    hipLaunchKernelGGL((p3_col0<N, DT>), dim3(cnt * N), dim3(2 * C::T), lds_c0, s, bt);
+    using G0 = Col0<N, DT>;
+    hipLaunchKernelGGL((p3_col0<N, DT>), dim3(cnt * G0::groups), dim3(2 * C::T * G0::G), G0::lds, s, bt);
     mark(3);
     if ((e = launch_p24<N, DT>(bt, s, v24, false)) != hipSuccess) return e;
     mark(4);
