@@ -354,8 +354,8 @@ struct P3Rows {
 // forward transform; see kLean).  Longer plans are left unbounded, where a
 // bound would only force spills.
 constexpr int p3_waves(int e, int threads, bool f32, bool seq) {
-    if (!seq || e > 8) return 1;
-    return f32 && threads > 256 ? 6 : 3;
+    if (!seq || e > (f32 ? 20 : 8)) return 1;
+    return f32 && threads > 256 && e <= 8 ? 6 : 3;
 }
 
 template <int N, int DT, int B, int TT, int SL, bool SEQ>
@@ -726,11 +726,11 @@ struct Sched {
         d24, pick_tile(N, odd > 1 ? TileV{C::BS, N / eh} : TileV{C::BS, N / e16}, d24, C::CX),
         pick_tile(N, {C::BS, C::T24, 1, true}, d24, C::CX)};
     // P3: one row per workgroup; the row pair k1, M-k1 per workgroup (sizes with
-    // an odd factor: half the elements per thread); or one row with the chains
-    // exchanged one at a time
+    // an odd factor: with the chains exchanged one at a time); or one row with
+    // the chains exchanged one at a time
     static constexpr TileV v3[3] = {
         d3,
-        pick_tile3(N, odd > 1 ? TileV{C::BP3, N / eh, 1} : TileV{C::BP3, C::T3, 2}, d3, C::CX, C::BS),
+        pick_tile3(N, odd > 1 ? TileV{C::BP3, C::T3, 2, true} : TileV{C::BP3, C::T3, 2}, d3, C::CX, C::BS),
         pick_tile3(N, {C::BP3, C::T3, 1, true}, d3, C::CX, C::BS)};
     static_assert(tile_ok(N, d24, C::CX) && tile_ok(N, d3, C::CX), "default tiles must fit");
 };
