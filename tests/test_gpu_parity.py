@@ -284,7 +284,7 @@ def test_batched_after_plan_destroyed():
 
 
 @pytest.mark.parametrize("n", [24, 48, 96, 128, 160, 256])
-@pytest.mark.parametrize("dtype", ["f32", "f64"])
+@pytest.mark.parametrize("dtype", ["f32", "f64", "split"])
 def test_every_schedule_candidate(n, dtype):
     """All compiled tile candidates of the strided passes give the oracle's result."""
     torch = torch_cuda()
