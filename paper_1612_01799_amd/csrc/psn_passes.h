@@ -348,11 +348,12 @@ struct P3Rows {
     static constexpr bool value = N >= 512;
 };
 
-// Minimum waves per SIMD asked of the compiler for P3: the one-chain variant
-// uses little LDS, so with up to 8 elements per thread it asks for enough
-// waves for three workgroups per CU (FP32 keeps few values live across the
-// forward transform; see kLean).  Longer plans are left unbounded, where a
-// bound would only force spills.
+// Minimum waves per SIMD asked of the compiler for P3.  The one-chain variant
+// uses little LDS, so it asks for three waves per SIMD (six for 512-thread
+// FP32 workgroups with up to 8 elements per thread: three workgroups per CU).
+// FP32 keeps few values live across the forward transform (see kLean), so
+// this holds up to 20 elements per thread; FP64 arithmetic only up to 8.
+// Longer plans are left unbounded, where a bound would only force spills.
 constexpr int p3_waves(int e, int threads, bool f32, bool seq) {
     if (!seq || e > (f32 ? 20 : 8)) return 1;
     return f32 && threads > 256 && e <= 8 ? 6 : 3;
@@ -432,9 +433,10 @@ p3_conv(const Batch<DT> bt) {
         x[e] = w2.ld(xb(e), xl);
         w[e] = tw[Ff::in_pos(t, e)];
     }
-    // The one-chain variant keeps fewer values live across the forward
-    // transform (more waves fit): it loads the kernel values after it and
-    // reloads the twiddles w at the end.
+    // FP32 variants with the one-chain exchange or more than 8 elements per
+    // thread keep fewer values live across the forward transform (more waves
+    // fit): they load the kernel values after it and reload the twiddles w at
+    // the end.  The FP64-arithmetic variants measured faster with early loads.
     constexpr bool kLean = DT == DT_F32 && (SEQ || E > 8);
     auto load_k = [&]() {
 #pragma unroll
@@ -484,8 +486,8 @@ p3_conv(const Batch<DT> bt) {
 // and k2 = n planes.  With the partner row -k the product is
 // Z' = a Z(k) + b conj(Z(-k)), a = (K0+Kn)/2 (stored in K's column 0) and
 // b = (K0-Kn)/2 (stored in Kb).  A row pair is rows q and M-q (row 0 pairs
-// with itself, as does row n); a workgroup holds col0_pairs(N) row pairs so
-// that short lines still fill a 64-lane wave.
+// with itself, as does row n); a workgroup holds Col0::G row pairs so that
+// short lines still fill a 64-lane wave.
 template <int N, int DT>
 struct Col0 {
     static constexpr int T = Cfg<N, DT>::T;
