@@ -205,8 +205,8 @@ def main():
                     help="also run one 1 GiB device-to-device tensor copy (reference for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on exactly one GPU; --gpus {args.gpus} is not supported by this build "
-              "(independent batches shard across GPUs without communication; see the design notes)",
+        print(f"bench.py measures exactly one GPU; --gpus {args.gpus} is not supported "
+              "(independent solves shard across GPUs with no communication between them)",
               file=sys.stderr)
         sys.exit(2)
 
