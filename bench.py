@@ -43,6 +43,30 @@ def workload(n):
     raise SystemExit(f"no workload for n={n}")
 
 
+def host_cpu():
+    """Host facts for the CPU baseline: logical CPUs, CPUs this process may use, model name."""
+    model = None
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    try:
+        allowed = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        allowed = os.cpu_count()
+    return {"nproc": os.cpu_count(), "affinity": allowed, "model": model}
+
+
+def oracle_workers():
+    """Threads for the oracle's FFTs: the CPUs this process may use, capped at
+    the 16 host CPUs that go with one GPU on the measurement box."""
+    h = host_cpu()
+    return max(1, min(16, h["affinity"] or 1))
+
+
 def pass_bytes(n, dtype):
     bio, bs, bk = {"f32": (4, 4, 4), "f64": (8, 8, 8), "split": (8, 6, 8)}[dtype]
     n3 = float(n) ** 3
@@ -141,7 +165,7 @@ def bench_batched(psn, torch, np, steps, warmup, with_oracle):
             n, L = mix.box.n[0], mix.box.b[0]
             if n not in sym:
                 sym[n] = O.half_spectrum(O.kernel_spectrum(mix.box, 1e-12))
-            ref = O.solve(W.mixture_density(mix), sym[n], workers=min(16, os.cpu_count() or 1))
+            ref = O.solve(W.mixture_density(mix), sym[n], workers=oracle_workers())
             worst = max(worst, float(np.max(np.abs(u.double().cpu().numpy() - ref)) / np.max(np.abs(ref))))
         out["max_rel_err_vs_oracle"] = worst
     return out
@@ -167,7 +191,7 @@ def bench_size(psn, torch, np, n, steps, warmup, with_oracle):
     out["max_rel_err_vs_oracle"] = None
     if with_oracle:
         import oracle as O
-        ref = O.solve(rho_np, O.half_spectrum(O.kernel_spectrum(mix.box, 1e-12)), workers=min(16, os.cpu_count() or 1))
+        ref = O.solve(rho_np, O.half_spectrum(O.kernel_spectrum(mix.box, 1e-12)), workers=oracle_workers())
         out["max_rel_err_vs_oracle"] = {k: float(np.max(np.abs(v - ref)) / np.max(np.abs(ref))) for k, v in us.items()}
     return out
 
@@ -273,17 +297,25 @@ def main():
     errs = {}
     if not args.no_cpu:
         import oracle as O
-        workers = min(16, os.cpu_count() or 1)
-        log(f"oracle kernel spectrum (setup, untimed), {workers} threads")
+        workers = oracle_workers()
+        host = host_cpu()
+        log(f"oracle kernel spectrum (setup, untimed), {workers} threads; host {host}")
         H = O.half_spectrum(O.kernel_spectrum(mix.box, 1e-12))
-        log("oracle solve (timed)")
-        t = time.perf_counter()
-        uref = O.solve(rho_np, H, workers=workers)
-        dt_cpu = time.perf_counter() - t
+        reps = 3
+        log(f"oracle solve (timed, {reps} runs)")
+        times = []
+        for _ in range(reps):
+            t = time.perf_counter()
+            uref = O.solve(rho_np, H, workers=workers)
+            times.append(time.perf_counter() - t)
+        dt_cpu = float(np.median(times))
         del H
         cpu = {"value": n ** 3 / dt_cpu, "unit": "grid pts/s", "cores": workers, "kind": "oracle",
-               "sample": f"one full FP64 oracle solve of the same n={n} workload (unpruned padded rfftn/irfftn, "
-                         f"scipy.fft with {workers} workers; kernel spectrum built beforehand), {dt_cpu:.1f} s"}
+               "sample": f"{reps} full FP64 oracle solves of the same n={n} workload (unpruned padded "
+                         f"rfftn/irfftn, scipy.fft with {workers} workers; kernel spectrum built beforehand), "
+                         f"median {dt_cpu:.2f} s of " + ", ".join(f"{v:.2f}" for v in times) + " s",
+               "host_nproc": host["nproc"], "host_cpus_allowed": host["affinity"], "host_cpu_model": host["model"],
+               "workers_rule": "min(16, CPUs allowed): the host CPU share of one GPU on the measurement box"}
         scale = float(np.max(np.abs(uref)))
         for k, v in u_host.items():
             errs[k] = float(np.max(np.abs(v - uref)) / scale)

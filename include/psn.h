@@ -74,7 +74,8 @@ typedef struct {
     double h3[3];       /* grid spacing per axis */
     double T3[3];       /* kernel truncation per axis */
     int schedule[2];    /* tile candidates of the axis-1 passes and of the axis-0 pass */
-    int tuned;          /* 1 if the schedule came from the autotuner */
+    int tuned;          /* 1 if the schedule came from the autotuner (or its cache file) */
+    int device;         /* HIP device the kernel spectrum was built on; -1 before the build */
 } psn_plan_info;
 
 /* Create a plan for an n^3 grid on [-L, L]^3 (the solver construction of the
@@ -100,6 +101,10 @@ psn_status psn_plan_create_box(int n, const double *a, const double *b, double t
  * the solve workspace.  Then picks the tile schedule of the strided passes:
  * each has three compiled candidates, timed once per (n, precision) in the
  * process on this plan's workspace (set PSN_TUNE=0 to keep the defaults).
+ * With PSN_TUNE_CACHE naming a file, a schedule recorded there for the same
+ * (n, precision) is taken without timing, and a newly timed one is appended,
+ * so that separate processes pick the same candidates (candidates agree only
+ * within rounding, see psn_plan_set_schedule).
  * Synchronises `stream` before returning.  Idempotent.
  * Errors: PSN_EINVAL, PSN_ENOMEM, PSN_EDEVICE. */
 psn_status psn_kernel_build(psn_plan *p, void *stream);
@@ -112,14 +117,17 @@ psn_status psn_kernel_build(psn_plan *p, void *stream);
 psn_status psn_solve(psn_plan *p, const void *rho, void *u, void *stream);
 
 /* Enqueue `count` independent solves, possibly of different sizes, as one
- * batch (many densities on one device).  plans[i], rho[i], u[i] as for
- * psn_solve; the same plan may appear more than once.  Each entry runs in its
- * own region of a per-device workspace arena (grown on demand, which
- * synchronises the device; held until the process ends), entries of one
- * (n, precision) share each kernel launch, and the launch sequence is
- * captured once per argument list into a HIP graph and replayed.  The arena
- * is shared by all batched calls on a device, so such calls must not overlap
- * across streams.  count == 0 does nothing.
+ * batch (many densities on one device).  This is the reuse of a set-up solver
+ * for many right-hand sides (paper section 4: construction once, then any
+ * number of solves without renewed setup), spread over several geometries at
+ * once.  plans[i], rho[i], u[i] as for psn_solve; the same plan may appear
+ * more than once.  Each entry runs in its own region of a per-device
+ * workspace arena (grown on demand, which synchronises the device; held until
+ * the process ends), entries of one (n, precision, schedule) share each
+ * kernel launch, and the launch sequence is captured once per argument list
+ * and schedule set into a HIP graph and replayed.  The arena is shared by all
+ * batched calls on a device, so such calls must not overlap across streams.
+ * count == 0 does nothing.
  * Errors: as psn_solve, for the first bad entry; PSN_ENOMEM if the arena
  * cannot grow. */
 psn_status psn_solve_batched(int count, psn_plan *const *plans,
@@ -134,11 +142,19 @@ psn_status psn_solve_batched(int count, psn_plan *const *plans,
 psn_status psn_solve_timed(psn_plan *p, const void *rho, void *u, void *stream, double *pass_ms);
 
 /* Override the tile schedule: candidate p24 (0..2) for the axis-1 passes and
- * p3 (0..2) for the axis-0 pass.  Every candidate computes the same result.
- * Errors: PSN_EINVAL. */
+ * p3 (0..2) for the axis-0 pass.  Every candidate computes the same
+ * transform; results agree within rounding but not bitwise, since a
+ * candidate may run another radix plan or another order of operations.  For
+ * one candidate the result is bitwise reproducible.  Errors: PSN_EINVAL. */
 psn_status psn_plan_set_schedule(psn_plan *p, int p24, int p3);
 
-/* Fill *info.  Errors: PSN_EINVAL. */
+/* Fill *info: the discretisation and error-control parameters of the paper's
+ * sections 2-3 as this plan derived them (grid spacing h from the section 4
+ * grid, truncation T, padded period, near-zone radius delta from the section
+ * 3 heuristic, the Gaussian-sum step, term count and achieved tolerance eps,
+ * the correction constants C0 and C2 once built), plus the device, memory,
+ * algorithmic HBM bytes per solve and the tile schedule.  Host only.
+ * Errors: PSN_EINVAL. */
 psn_status psn_plan_query(const psn_plan *p, psn_plan_info *info);
 
 /* Copy the Gaussian-sum table to host arrays tau[cap], w[cap] (section 2:

@@ -46,7 +46,7 @@ class PlanInfo(ctypes.Structure):
         ("C2", ctypes.c_double), ("built", ctypes.c_int), ("device_bytes", ctypes.c_size_t),
         ("algorithmic_bytes", ctypes.c_double), ("a", ctypes.c_double * 3), ("b", ctypes.c_double * 3),
         ("h3", ctypes.c_double * 3), ("T3", ctypes.c_double * 3), ("schedule", ctypes.c_int * 2),
-        ("tuned", ctypes.c_int),
+        ("tuned", ctypes.c_int), ("device", ctypes.c_int),
     ]
 
 
@@ -134,6 +134,7 @@ class Plan:
     # -- setup
     def build(self, stream=None) -> "Plan":
         _check(_lib.psn_kernel_build(self._h, _stream_handle(stream)), "psn_kernel_build")
+        self._dev = self.info()["device"]
         return self
 
     # -- solve
@@ -141,15 +142,40 @@ class Plan:
         import torch
         return torch.float32 if self.dtype == F32 else torch.float64
 
-    def solve(self, rho, out=None, stream=None):
+    def device(self) -> int:
+        """HIP device the kernel spectrum was built on (-1 before build())."""
+        return getattr(self, "_dev", -1)
+
+    def _check_io(self, rho, out, what):
+        """Every pointer handed to the kernels must be a contiguous CUDA tensor
+        of the plan's shape and I/O dtype on the plan's device: a host pointer
+        reaching a kernel is a GPU page fault, a wrong dtype a wrong result."""
         import torch
         n = self.n
-        if rho.shape != (n, n, n) or rho.dtype != self.io_dtype() or not rho.is_cuda or not rho.is_contiguous():
-            raise ValueError(f"rho must be a contiguous ({n},{n},{n}) {self.io_dtype()} CUDA tensor")
+        for name, t in (("rho", rho), ("out", out)):
+            if not isinstance(t, torch.Tensor):
+                raise ValueError(f"{what}: {name} must be a torch tensor")
+            if not t.is_cuda:
+                raise ValueError(f"{what}: {name} must be a CUDA tensor (got device {t.device})")
+            if tuple(t.shape) != (n, n, n) or t.dtype != self.io_dtype() or not t.is_contiguous():
+                raise ValueError(f"{what}: {name} must be a contiguous ({n},{n},{n}) {self.io_dtype()} tensor, "
+                                 f"got {tuple(t.shape)} {t.dtype} contiguous={t.is_contiguous()}")
+        dev = self.device()
+        if dev < 0:
+            return  # not built: the library reports PSN_ESTATE before any launch
+        cur = torch.cuda.current_device()
+        for name, t in (("rho", rho), ("out", out)):
+            if t.device.index != dev or dev != cur:
+                raise ValueError(f"{what}: {name} is on cuda:{t.device.index}, the plan on cuda:{dev}, "
+                                 f"the current device is cuda:{cur}")
+
+    def solve(self, rho, out=None, stream=None):
+        import torch
+        if not isinstance(rho, torch.Tensor) or not rho.is_cuda:
+            raise ValueError("psn_solve: rho must be a CUDA tensor")
         if out is None:
             out = torch.empty_like(rho)
-        elif out.shape != rho.shape or out.dtype != rho.dtype or not out.is_contiguous():
-            raise ValueError("out must match rho")
+        self._check_io(rho, out, "psn_solve")
         _check(_lib.psn_solve(self._h, ctypes.c_void_p(rho.data_ptr()), ctypes.c_void_p(out.data_ptr()),
                               _stream_handle(stream)), "psn_solve")
         return out
@@ -157,6 +183,7 @@ class Plan:
     def solve_timed(self, rho, out, stream=None):
         """One solve with per-pass HIP events; returns the five pass times in ms."""
         import numpy as np
+        self._check_io(rho, out, "psn_solve_timed")
         ms = np.zeros(5)
         _check(_lib.psn_solve_timed(self._h, ctypes.c_void_p(rho.data_ptr()), ctypes.c_void_p(out.data_ptr()),
                                     _stream_handle(stream), ms.ctypes.data_as(ctypes.POINTER(ctypes.c_double))),
@@ -211,21 +238,27 @@ class Plan:
             pass
 
 
-def solve_batched(plans, rhos, outs=None, stream=None):
-    """Enqueue one batch of solves (sizes may differ); returns the outputs."""
+def _batch_args(plans, rhos, outs, what):
     import torch
     count = len(plans)
-    if len(rhos) != count:
-        raise ValueError("plans and rhos differ in length")
+    if len(rhos) != count or (outs is not None and len(outs) != count):
+        raise ValueError("plans, rhos and outs differ in length")
+    for r in rhos:
+        if not isinstance(r, torch.Tensor) or not r.is_cuda:
+            raise ValueError(f"{what}: every rho must be a CUDA tensor")
     if outs is None:
         outs = [torch.empty_like(r) for r in rhos]
-    for p, r, o in zip(plans, rhos, outs):
-        n = p.n
-        if r.shape != (n, n, n) or r.dtype != p.io_dtype() or not r.is_contiguous() or o.shape != r.shape:
-            raise ValueError("batch entry does not match its plan")
+    for i, (p, r, o) in enumerate(zip(plans, rhos, outs)):
+        p._check_io(r, o, f"{what} entry {i}")
     P = ctypes.c_void_p
     hp = (P * count)(*[p.handle for p in plans])
     hr = (P * count)(*[P(r.data_ptr()) for r in rhos])
     ho = (P * count)(*[P(o.data_ptr()) for o in outs])
+    return count, hp, hr, ho, outs
+
+
+def solve_batched(plans, rhos, outs=None, stream=None):
+    """Enqueue one batch of solves (sizes may differ); returns the outputs."""
+    count, hp, hr, ho, outs = _batch_args(plans, rhos, outs, "psn_solve_batched")
     _check(_lib.psn_solve_batched(count, hp, hr, ho, _stream_handle(stream)), "psn_solve_batched")
     return outs

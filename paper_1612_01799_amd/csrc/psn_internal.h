@@ -40,6 +40,11 @@ struct psn_plan {
     bool tuned = false;
 };
 
+namespace psn {
+// problems per launch of one pass kernel (the by-value launch table)
+constexpr int kMaxBatchHost = 32;
+}
+
 namespace psn_host {
 
 // Kernel spectrum layout: planes of (n+1) x n reals per folded k~1, each tiled

@@ -141,7 +141,7 @@ struct Cfg {
 // One launch serves up to kMaxBatch problems of the same size.  The table
 // travels by value in the kernel arguments (no device copy, capturable in a
 // graph); workgroup units are numbered problem-major.
-constexpr int kMaxBatch = 32;
+constexpr int kMaxBatch = kMaxBatchHost;
 
 template <int DT>
 struct Prob {
@@ -898,7 +898,7 @@ Prob<DT> prob_of(const psn_host::Slot& sl) {
     return pr;
 }
 
-// Slots [0, count) share n and precision; the first slot's plan gives the schedule.
+// Slots [0, count) share n, precision and schedule (the caller groups them so).
 template <int DT>
 hipError_t solve_group(const psn_host::Slot* slots, int count, hipStream_t s, hipEvent_t* ev) {
     const int v24 = slots[0].plan->sched24, v3 = slots[0].plan->sched3;

@@ -3,7 +3,10 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
+#include <cstdint>
 #include <cmath>
+#include <cstdio>
 #include <cstdlib>
 #include <cstring>
 #include <map>
@@ -143,29 +146,66 @@ void free_device(psn_plan* p) {
 bool is_real_dtype(int d) { return d == PSN_F64 || d == PSN_F32 || d == PSN_SPLIT; }
 
 // Autotuned schedules, once per (n, precision) and process.  PSN_TUNE=0 keeps
-// the default tiles.
+// the default tiles.  PSN_TUNE_CACHE names a text file of lines
+// "n precision p24 p3": a recorded schedule is taken without timing and a
+// newly timed one is appended, so separate processes agree on the candidates.
 std::mutex g_tune_mutex;
 std::map<std::pair<int, int>, std::pair<int, int>> g_tuned;
+
+bool tune_cache_lookup(const char* path, int n, int dt, int* b24, int* b3) {
+    FILE* f = std::fopen(path, "r");
+    if (!f) return false;
+    int a, b, c, d;
+    bool found = false;
+    while (std::fscanf(f, "%d %d %d %d", &a, &b, &c, &d) == 4) {
+        if (a == n && b == dt && c >= 0 && c < psn_host::kScheduleCandidates && d >= 0 &&
+            d < psn_host::kScheduleCandidates) {
+            *b24 = c;
+            *b3 = d;
+            found = true;  // the last record of a key wins
+        }
+    }
+    std::fclose(f);
+    return found;
+}
+
+void tune_cache_append(const char* path, int n, int dt, int b24, int b3) {
+    FILE* f = std::fopen(path, "a");
+    if (!f) return;
+    std::fprintf(f, "%d %d %d %d\n", n, dt, b24, b3);
+    std::fclose(f);
+}
 
 psn_status tune_schedule(psn_plan* p, hipStream_t s) {
     const char* env = std::getenv("PSN_TUNE");
     if (env && env[0] == '0') return PSN_OK;
+    const char* cache = std::getenv("PSN_TUNE_CACHE");
+    if (cache && !cache[0]) cache = nullptr;
     std::lock_guard<std::mutex> lock(g_tune_mutex);
     const auto key = std::make_pair(p->n, int(p->dtype));
-    auto it = g_tuned.find(key);
-    if (it == g_tuned.end()) {
-        int b24 = 0, b3 = 0;
-        hipError_t e = hipErrorInvalidValue;
-        switch (p->dtype) {
-            case PSN_F64: e = psn_host::tune_f64(p, s, &b24, &b3); break;
-            case PSN_F32: e = psn_host::tune_f32(p, s, &b24, &b3); break;
-            case PSN_SPLIT: e = psn_host::tune_split(p, s, &b24, &b3); break;
+    int b24 = 0, b3 = 0;
+    if (cache && tune_cache_lookup(cache, p->n, int(p->dtype), &b24, &b3)) {
+        // the recorded choice wins over this process's own timing
+        g_tuned[key] = std::make_pair(b24, b3);
+    } else {
+        auto it = g_tuned.find(key);
+        if (it != g_tuned.end()) {
+            b24 = it->second.first;
+            b3 = it->second.second;
+        } else {
+            hipError_t e = hipErrorInvalidValue;
+            switch (p->dtype) {
+                case PSN_F64: e = psn_host::tune_f64(p, s, &b24, &b3); break;
+                case PSN_F32: e = psn_host::tune_f32(p, s, &b24, &b3); break;
+                case PSN_SPLIT: e = psn_host::tune_split(p, s, &b24, &b3); break;
+            }
+            if (!hip_ok(e, "schedule tuning")) return PSN_EDEVICE;
+            g_tuned.emplace(key, std::make_pair(b24, b3));
         }
-        if (!hip_ok(e, "schedule tuning")) return PSN_EDEVICE;
-        it = g_tuned.emplace(key, std::make_pair(b24, b3)).first;
+        if (cache) tune_cache_append(cache, p->n, int(p->dtype), b24, b3);
     }
-    p->sched24 = it->second.first;
-    p->sched3 = it->second.second;
+    p->sched24 = b24;
+    p->sched3 = b3;
     p->tuned = true;
     return PSN_OK;
 }
@@ -228,7 +268,11 @@ struct BatchCache {
     std::vector<hipEvent_t> join;
     hipEvent_t fork = nullptr;
     std::map<std::vector<const void*>, hipGraphExec_t> graphs;
+    // A graph may still run on the stream it was launched on (any stream of
+    // the caller's), so the device is drained before any is destroyed.
     void clear_graphs() {
+        if (graphs.empty()) return;
+        (void)hipDeviceSynchronize();
         for (auto& g : graphs) (void)hipGraphExecDestroy(g.second);
         graphs.clear();
     }
@@ -475,22 +519,27 @@ psn_status psn_solve_batched(int count, psn_plan* const* plans, const void* cons
         bc.arena_bytes = need;
     }
 
-    // the launch sequence is captured once per argument list and replayed
+    // the launch sequence is captured once per argument list and schedule set
+    // and replayed; a plan's schedule is fixed in the graph at capture
     std::vector<const void*> key;
-    key.reserve(3 * count);
+    key.reserve(4 * count);
     for (int i = 0; i < count; ++i) {
         key.push_back(plans[i]);
         key.push_back(rho[i]);
         key.push_back(u[i]);
+        key.push_back(reinterpret_cast<const void*>(
+            static_cast<uintptr_t>(plans[i]->sched24 * psn_host::kScheduleCandidates + plans[i]->sched3)));
     }
     hipStream_t s = static_cast<hipStream_t>(stream);
     auto it = bc.graphs.find(key);
     if (it == bc.graphs.end()) {
-        // group entries by (n, precision), keeping the order within a group
-        std::map<std::pair<int, int>, std::vector<psn_host::Slot>> groups;
+        // group entries by (n, precision, schedule), keeping the order within a
+        // group: a group shares each launch, so its entries share one schedule
+        std::map<std::array<int, 4>, std::vector<psn_host::Slot>> groups;
         for (int i = 0; i < count; ++i) {
             const psn_plan* p = plans[i];
-            groups[{p->n, p->dtype}].push_back(arena_slot(p, rho[i], u[i], static_cast<char*>(bc.arena) + off[i]));
+            groups[{p->n, int(p->dtype), p->sched24, p->sched3}].push_back(
+                arena_slot(p, rho[i], u[i], static_cast<char*>(bc.arena) + off[i]));
         }
         // Chains: groups in decreasing order of HBM bytes, each appended to the
         // chain with the fewest bytes so far (longest-first list scheduling),
@@ -571,6 +620,7 @@ psn_status psn_plan_query(const psn_plan* p, psn_plan_info* info) {
     info->schedule[0] = p->sched24;
     info->schedule[1] = p->sched3;
     info->tuned = p->tuned ? 1 : 0;
+    info->device = p->built ? p->device : -1;
     for (int q = 0; q < 3; ++q) {
         info->a[q] = p->a[q];
         info->b[q] = p->b[q];
@@ -643,8 +693,10 @@ void psn_plan_destroy(psn_plan* p) {
         for (auto& dc : g_batch)
             for (auto it = dc.second.graphs.begin(); it != dc.second.graphs.end();) {
                 bool uses = false;
-                for (size_t i = 0; i < it->first.size(); i += 3) uses |= it->first[i] == p;
+                for (size_t i = 0; i < it->first.size(); i += 4) uses |= it->first[i] == p;
                 if (uses) {
+                    // the graph may still be running on the caller's stream
+                    (void)hipDeviceSynchronize();
                     (void)hipGraphExecDestroy(it->second);
                     it = dc.second.graphs.erase(it);
                 } else {

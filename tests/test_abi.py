@@ -149,3 +149,16 @@ def test_strerror():
     for st in range(-6, 1):
         assert psn._lib.psn_strerror(st)
     assert psn._lib.psn_strerror(-99) == b"unknown status"
+
+
+def test_binding_rejects_host_tensors():
+    """A host tensor never reaches the kernels as a device pointer."""
+    import torch
+    p = psn.Plan(16, 1.0, 1e-12, "f32")
+    rho = torch.zeros((16, 16, 16), dtype=torch.float32)
+    with pytest.raises(ValueError):
+        p.solve(rho)
+    with pytest.raises(ValueError):
+        psn.solve_batched([p], [rho])
+    with pytest.raises(ValueError):
+        psn.solve_batched([p, p], [rho])

@@ -79,7 +79,9 @@ def test_random_density_all_frequencies(dtype):
     rho = np.random.default_rng(5).standard_normal((n, n, n))
     ref = O.solve(rho, oracle_symbol(n, L))
     u = gpu_solve(psn, torch, n, L, dtype, rho)
-    assert max_rel(u, ref) <= TOL[dtype] * 10
+    err = max_rel(u, ref)
+    print(f"white noise n={n} {dtype}: max rel err {err:.3e}", flush=True)
+    assert err <= TOL[dtype]
 
 
 def _gpu_entries():
@@ -178,6 +180,42 @@ def test_side_stream():
     assert max_rel(u.cpu().numpy(), O.solve(rho_np, oracle_symbol(n, L))) <= TOL["f64"]
 
 
+def test_batched_full_mixed_size_workload():
+    """The whole mixed-size workload: 64 seeded densities with edges drawn from
+    {48, 64, 96, 128, 160} (h = 0.1), FP32, in ONE batched call (the launch
+    configuration the benchmark times); every problem against the oracle."""
+    torch = torch_cuda()
+    mixes = W.config_batched()
+    assert len(mixes) == 64 and {m.box.n[0] for m in mixes} == set(W.BATCH_EDGES)
+    plans, rhos, refs = _batch_case(torch, mixes, "f32")
+    outs = psn.solve_batched(plans, rhos)
+    torch.cuda.synchronize()
+    errs = [max_rel(u.double().cpu().numpy(), ref) for u, ref in zip(outs, refs)]
+    print(f"64-problem batch: worst max rel err {max(errs):.3e}", flush=True)
+    assert max(errs) <= TOL["f32"]
+
+
+def test_batched_odd_sizes_f32_and_split():
+    """n = 96 (factor 3) and n = 160 (factor 5) inside one batch graph, in FP32
+    and in split precision, beside a power-of-two size."""
+    torch = torch_cuda()
+    mixes = W.config_batched(seed=2024, count=40)
+    pick = []
+    for n in (96, 160, 64):
+        pick += [m for m in mixes if m.box.n[0] == n][:2]
+    assert {m.box.n[0] for m in pick} == {96, 160, 64}
+    p32, r32, ref32 = _batch_case(torch, pick, "f32")
+    psp, rsp, refsp = _batch_case(torch, pick, "split")
+    outs = psn.solve_batched(p32 + psp, r32 + rsp)
+    torch.cuda.synchronize()
+    k = len(pick)
+    for i, (u, ref) in enumerate(zip(outs, ref32 + refsp)):
+        dt = "f32" if i < k else "split"
+        err = max_rel(u.double().cpu().numpy(), ref)
+        print(f"odd-size batch entry {i} n={pick[i % k].box.n[0]} {dt}: {err:.3e}", flush=True)
+        assert err <= TOL[dt]
+
+
 def test_batched_mixed_sizes():
     torch = torch_cuda()
     mixes = W.config_batched(count=10)
@@ -251,8 +289,9 @@ def test_batched_repeated_plan_graph_replay_and_chunking():
         r.copy_(torch.from_numpy(rhos_np[i]))
     psn.solve_batched([plan] * 40, rhos, outs)
     torch.cuda.synchronize()
-    for u, r in zip(outs, rhos_np):
-        assert max_rel(u.double().cpu().numpy(), O.solve(r, sym)) <= 10 * TOL["f32"]
+    worst = max(max_rel(u.double().cpu().numpy(), O.solve(r, sym)) for u, r in zip(outs, rhos_np))
+    print(f"graph replay with new values: worst max rel err {worst:.3e}", flush=True)
+    assert worst <= TOL["f32"]
 
 
 def test_batched_mixed_precisions_and_sizes():
@@ -312,3 +351,64 @@ def test_every_schedule_candidate_n512():
         plan.set_schedule(*s)
         u = gpu_solve(psn, torch, 512, 12.0, "f32", _cache512["rho"], plan=plan)
         assert max_rel(u, _cache512["ref"]) <= TOL["f32"], s
+
+
+@pytest.mark.parametrize("n", [96, 128])
+@pytest.mark.parametrize("dtype", ["f32", "f64", "split"])
+def test_bitwise_determinism_every_schedule(n, dtype):
+    """Repeated solves give bitwise-equal results under every schedule the
+    autotuner may pick (a race in an LDS exchange or a missing barrier would
+    show up as run-to-run differences)."""
+    torch = torch_cuda()
+    L = 2.0 + n / 64.0
+    rho_np = _mix(n, L, 500 + n)
+    plan = psn.Plan(n, L, 1e-12, dtype).build()
+    rho = torch.from_numpy(rho_np).to("cuda", plan.io_dtype())
+    for v24 in range(3):
+        for v3 in range(3):
+            plan.set_schedule(v24, v3)
+            a = plan.solve(rho)
+            b = plan.solve(rho)
+            c = plan.solve(rho)
+            torch.cuda.synchronize()
+            assert torch.equal(a, b) and torch.equal(a, c), (v24, v3)
+
+
+def test_binding_rejects_bad_tensors_before_launch():
+    """Wrong device, dtype, shape or layout raises ValueError in the binding;
+    nothing reaches the kernels."""
+    torch = torch_cuda()
+    n = 16
+    plan = psn.Plan(n, 1.5, 1e-12, "f32").build()
+    assert plan.device() == torch.cuda.current_device()
+    rho = torch.zeros((n, n, n), device="cuda", dtype=torch.float32)
+    bad_outs = [torch.zeros((n, n, n), dtype=torch.float32),                       # host memory
+                torch.zeros((n, n, n), device="cuda", dtype=torch.float64),        # wrong dtype
+                torch.zeros((n, n, 2 * n), device="cuda", dtype=torch.float32)[:, :, ::2],  # strided
+                torch.zeros((n, n, n + 1), device="cuda", dtype=torch.float32)]    # wrong shape
+    for o in bad_outs:
+        with pytest.raises(ValueError):
+            plan.solve(rho, out=o)
+        with pytest.raises(ValueError):
+            psn.solve_batched([plan], [rho], [o])
+    with pytest.raises(ValueError):
+        plan.solve(rho.double())
+    with pytest.raises(ValueError):
+        psn.solve_batched([plan], [rho.double()])
+    with pytest.raises(ValueError):
+        psn.solve_batched([plan], [rho], [])
+
+
+def test_tune_cache_file(tmp_path, monkeypatch):
+    """PSN_TUNE_CACHE: a recorded schedule is taken without timing; a plan
+    whose (n, precision) has no record appends one."""
+    torch_cuda()
+    path = tmp_path / "tune.txt"
+    path.write_text("32 1 2 1\n")
+    monkeypatch.setenv("PSN_TUNE_CACHE", str(path))
+    plan = psn.Plan(32, 2.5, 1e-12, "f32").build()
+    info = plan.info()
+    assert info["schedule"] == (2, 1) and info["tuned"] == 1
+    plan2 = psn.Plan(16, 1.5, 1e-12, "f64").build()
+    recs = [tuple(int(v) for v in line.split()) for line in path.read_text().split("\n") if line.strip()]
+    assert (16, 0) + tuple(plan2.info()["schedule"]) in recs
