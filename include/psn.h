@@ -50,7 +50,8 @@ typedef enum {
     PSN_ENOMEM = -3,  /* device allocation failed */
     PSN_EDEVICE = -4, /* a HIP call or kernel launch failed */
     PSN_ESTATE = -5,  /* psn_solve before psn_kernel_build */
-    PSN_EFIT = -6     /* the Gaussian-sum fit missed tol on [delta, R] */
+    PSN_EFIT = -6,    /* the Gaussian-sum fit missed tol on [delta, R] */
+    PSN_ELIMIT = -7   /* a fixed limit of psn_solve_batched_noalloc exceeded */
 } psn_status;
 
 typedef struct {
@@ -132,6 +133,24 @@ psn_status psn_solve(psn_plan *p, const void *rho, void *u, void *stream);
  * cannot grow. */
 psn_status psn_solve_batched(int count, psn_plan *const *plans,
                              const void *const *rho, void *const *u, void *stream);
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * batch as psn_solve_batched, with the same results, but it allocates
+ * nothing.  The workspace of every entry comes from one fixed device array of
+ * 256 MiB per device, compiled into the library and held until the process
+ * ends (e.g. two n = 160 FP32 entries or ten n = 96 ones fit; one entry needs
+ * about 24 n^3 bytes in FP32, 48 n^3 in F64 and SPLIT).  No graph is captured:
+ * the launches are enqueued on `stream` directly, entries of one
+ * (n, precision, schedule) sharing each launch.  plans, rho, u as for
+ * psn_solve_batched; the plans must have been built (which also looks the
+ * array up on their device).  Every call on a device uses the same array, so
+ * calls that overlap on one device (any streams, any plans) race; order them
+ * on one stream or synchronise between them.
+ * Errors: as psn_solve_batched; PSN_ELIMIT (nothing enqueued) if the entries'
+ * workspace exceeds the array or count exceeds 1024. */
+psn_status psn_solve_batched_noalloc(int count, psn_plan *const *plans,
+                                     const void *const *rho, void *const *u, void *stream);
 
 /* As psn_solve, but also records a HIP event on `stream` before the first
  * pass and after each of the five passes (P1 axis-2 real-to-complex, P2

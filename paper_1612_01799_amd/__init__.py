@@ -17,7 +17,7 @@ from __future__ import annotations
 import ctypes
 import os
 
-__all__ = ["Plan", "PsnError", "solve_batched", "size_supported", "library_path",
+__all__ = ["Plan", "PsnError", "solve_batched", "solve_batched_noalloc", "size_supported", "library_path",
            "F64", "F32", "SPLIT", "STATUS"]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -26,7 +26,7 @@ _LIB_PATH = os.path.join(_HERE, "libpsn.so")
 F64, F32, SPLIT = 0, 1, 2
 _DTYPES = {"f64": F64, "f32": F32, "split": SPLIT, F64: F64, F32: F32, SPLIT: SPLIT}
 STATUS = {0: "PSN_OK", -1: "PSN_EINVAL", -2: "PSN_ESIZE", -3: "PSN_ENOMEM", -4: "PSN_EDEVICE",
-          -5: "PSN_ESTATE", -6: "PSN_EFIT"}
+          -5: "PSN_ESTATE", -6: "PSN_EFIT", -7: "PSN_ELIMIT"}
 
 
 class PsnError(RuntimeError):
@@ -72,6 +72,8 @@ def _load():
         "psn_solve_timed": (ctypes.c_int, [P, P, P, P, ctypes.POINTER(ctypes.c_double)]),
         "psn_solve_batched": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(P), ctypes.POINTER(P),
                                              ctypes.POINTER(P), P]),
+        "psn_solve_batched_noalloc": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(P), ctypes.POINTER(P),
+                                                     ctypes.POINTER(P), P]),
         "psn_plan_query": (ctypes.c_int, [P, ctypes.POINTER(PlanInfo)]),
         "psn_plan_gs_table": (ctypes.c_int, [P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
                                              ctypes.c_int, ctypes.POINTER(ctypes.c_int)]),
@@ -261,4 +263,14 @@ def solve_batched(plans, rhos, outs=None, stream=None):
     """Enqueue one batch of solves (sizes may differ); returns the outputs."""
     count, hp, hr, ho, outs = _batch_args(plans, rhos, outs, "psn_solve_batched")
     _check(_lib.psn_solve_batched(count, hp, hr, ho, _stream_handle(stream)), "psn_solve_batched")
+    return outs
+
+
+def solve_batched_noalloc(plans, rhos, outs, stream=None):
+    """As solve_batched, through the entry point that allocates no device
+    memory (the workspace is the library's fixed scratch array); `outs` must
+    be given, so that the call itself allocates nothing either."""
+    count, hp, hr, ho, outs = _batch_args(plans, rhos, outs, "psn_solve_batched_noalloc")
+    _check(_lib.psn_solve_batched_noalloc(count, hp, hr, ho, _stream_handle(stream)),
+           "psn_solve_batched_noalloc")
     return outs

@@ -284,6 +284,32 @@ std::map<int, BatchCache> g_batch;
 // some of them back to back, in an order the runtime picks.
 constexpr size_t kBatchChains = 4;
 
+// Workspace of psn_solve_batched_noalloc: a fixed device array, so that call
+// makes no allocation.  Host code never passes `scratch` itself to a kernel
+// (in host code the name is a host-side stand-in, not a device address); it
+// uses the address hipGetSymbolAddress returns, looked up once per device with
+// that device current and kept in g_scratch_ptr.  Every call on a device shares
+// the array; the passes overwrite every workspace element they later read, so
+// nothing needs clearing between calls.
+constexpr size_t kScratchBytes = size_t(256) << 20;
+constexpr int kNoAllocMaxCount = 1024;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+std::mutex g_scratch_mutex;
+std::map<int, void*> g_scratch_ptr;
+
+// Address of this device's scratch array (the current device must be `dev`).
+bool scratch_ptr(int dev, void** out) {
+    std::lock_guard<std::mutex> lock(g_scratch_mutex);
+    auto it = g_scratch_ptr.find(dev);
+    if (it == g_scratch_ptr.end()) {
+        void* ptr = nullptr;
+        if (!hip_ok(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)), "hipGetSymbolAddress (scratch)")) return false;
+        it = g_scratch_ptr.emplace(dev, ptr).first;
+    }
+    *out = it->second;
+    return true;
+}
+
 }  // namespace
 
 namespace psn_host {
@@ -440,6 +466,11 @@ psn_status psn_kernel_build(psn_plan* p, void* stream) {
     }
     p->C0 = cc[0];
     p->C2 = cc[1];
+    void* sp = nullptr;
+    if (!scratch_ptr(p->device, &sp)) {  // set-up of the no-allocation batch entry point on this device
+        free_device(p);
+        return PSN_EDEVICE;
+    }
     p->built = true;
     return tune_schedule(p, s);
 }
@@ -607,6 +638,65 @@ psn_status psn_solve_batched(int count, psn_plan* const* plans, const void* cons
     return PSN_OK;
 }
 
+psn_status psn_solve_batched_noalloc(int count, psn_plan* const* plans, const void* const* rho, void* const* u,
+                                    void* stream) {
+    if (count < 0 || (count > 0 && (!plans || !rho || !u))) return PSN_EINVAL;
+    for (int i = 0; i < count; ++i) {
+        if (!plans[i] || !rho[i] || !u[i]) return PSN_EINVAL;
+        if (!plans[i]->built) return PSN_ESTATE;
+    }
+    g_last_error.clear();
+    if (count == 0) return PSN_OK;
+    if (count > kNoAllocMaxCount) {
+        g_last_error = "psn_solve_batched_noalloc: " + std::to_string(count) + " entries, at most " +
+                       std::to_string(kNoAllocMaxCount);
+        return PSN_ELIMIT;
+    }
+    (void)hipGetLastError();
+    int dev = -1;
+    if (!hip_ok(hipGetDevice(&dev), "hipGetDevice")) return PSN_EDEVICE;
+    size_t need = 0;
+    for (int i = 0; i < count; ++i) {
+        if (plans[i]->device != dev) return PSN_EINVAL;
+        need += slot_bytes(plans[i]);
+    }
+    if (need > kScratchBytes) {
+        g_last_error = "psn_solve_batched_noalloc: the batch needs " + std::to_string(need) +
+                       " workspace bytes, the fixed scratch area holds " + std::to_string(kScratchBytes);
+        return PSN_ELIMIT;
+    }
+    void* base = nullptr;
+    if (!scratch_ptr(dev, &base)) return PSN_EDEVICE;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    // Entry i's workspace starts at the sum of the earlier entries' sizes.
+    // Entries sharing (n, precision, schedule) share each launch; the groups
+    // run one after another on `stream`, found by repeated scans (no host or
+    // device allocation).
+    bool done[kNoAllocMaxCount] = {};
+    psn_host::Slot group[psn::kMaxBatchHost];
+    for (int i = 0; i < count; ++i) {
+        if (done[i]) continue;
+        const psn_plan* p0 = plans[i];
+        size_t off = 0;
+        int g = 0;
+        for (int j = 0; j < count; ++j) {
+            const psn_plan* pj = plans[j];
+            if (j >= i && !done[j] && pj->n == p0->n && pj->dtype == p0->dtype && pj->sched24 == p0->sched24 &&
+                pj->sched3 == p0->sched3) {
+                group[g++] = arena_slot(pj, rho[j], u[j], static_cast<char*>(base) + off);
+                done[j] = true;
+                if (g == psn::kMaxBatchHost) {
+                    if (!hip_ok(psn_host::launch_group(group, g, s), "batch launch")) return PSN_EDEVICE;
+                    g = 0;
+                }
+            }
+            off += slot_bytes(pj);
+        }
+        if (g > 0 && !hip_ok(psn_host::launch_group(group, g, s), "batch launch")) return PSN_EDEVICE;
+    }
+    return PSN_OK;
+}
+
 psn_status psn_plan_query(const psn_plan* p, psn_plan_info* info) {
     if (!p || !info) return PSN_EINVAL;
     std::memset(info, 0, sizeof *info);
@@ -719,6 +809,7 @@ const char* psn_strerror(psn_status st) {
         case PSN_EDEVICE: return "HIP call or kernel launch failed";
         case PSN_ESTATE: return "kernel spectrum not built";
         case PSN_EFIT: return "Gaussian-sum fit missed the tolerance";
+        case PSN_ELIMIT: return "request exceeds a fixed limit of the no-allocation entry point";
     }
     return "unknown status";
 }

@@ -146,7 +146,7 @@ def test_schedule_override_validation():
 
 
 def test_strerror():
-    for st in range(-6, 1):
+    for st in range(-7, 1):
         assert psn._lib.psn_strerror(st)
     assert psn._lib.psn_strerror(-99) == b"unknown status"
 
@@ -162,3 +162,18 @@ def test_binding_rejects_host_tensors():
         psn.solve_batched([p], [rho])
     with pytest.raises(ValueError):
         psn.solve_batched([p, p], [rho])
+
+
+def test_noalloc_batch_host_checks():
+    """Argument and state errors of the no-allocation batch are found on the
+    host before any device work."""
+    lib = psn._lib
+    p = psn.Plan(16, 1.0, 1e-12, "f32")
+    buf = ctypes.create_string_buffer(16 * 16 * 16 * 4)
+    P = ctypes.c_void_p
+    arr = (P * 1)(p.handle)
+    bufs = (P * 1)(ctypes.cast(buf, P))
+    assert lib.psn_solve_batched_noalloc(1, arr, bufs, bufs, None) == -5
+    assert lib.psn_solve_batched_noalloc(0, None, None, None, None) == 0
+    assert lib.psn_solve_batched_noalloc(-1, None, None, None, None) == -1
+    assert lib.psn_solve_batched_noalloc(1, None, None, None, None) == -1
