@@ -334,6 +334,15 @@ struct TwLds {
     }
 };
 
+// Twiddles of a half-length transform (length N/2 needs exp(-2 pi i m / N))
+// from the 2N-entry table of the full length: entry 2m.
+template <class Real>
+struct TwHalf {
+    static constexpr bool kRows = false;
+    TwLds<Real> full;
+    __device__ __forceinline__ cx<Real> operator()(int m) const { return full(2 * m); }
+};
+
 // Per-stage twiddle rows in LDS, laid out by TeamFFT::fill_rows: a thread
 // reads all R - 1 factors of a stage from one row.
 template <class Real>
@@ -408,8 +417,10 @@ struct TeamFFT {
             if (F2::radix(i) != radix(i)) return false;
         return true;
     }
-    // cooperative fill from the 2N-entry table tw2n (global); visible after the next barrier
-    template <int I = 1>
+    // cooperative fill from the 2N-entry table tw2n (global; with TS = 2,
+    // every other entry of the table of a transform twice as long); visible
+    // after the next barrier
+    template <int I = 1, int TS = 1>
     static __device__ __forceinline__ void fill_rows(cx<Real>* rows, const cx<Real>* __restrict__ tw2n, int tid,
                                                      int nthreads) {
         if constexpr (I < S) {
@@ -417,9 +428,9 @@ struct TeamFFT {
             cx<Real>* row0 = rows + rows_offset(I);
             for (int idx = tid; idx < Ns * RP; idx += nthreads) {
                 const int k = idx / RP, r = idx % RP + 1;
-                row0[idx] = r < R ? tw2n[r * k * step] : cx<Real>{Real(0), Real(0)};
+                row0[idx] = r < R ? tw2n[TS * r * k * step] : cx<Real>{Real(0), Real(0)};
             }
-            fill_rows<I + 1>(rows, tw2n, tid, nthreads);
+            fill_rows<I + 1, TS>(rows, tw2n, tid, nthreads);
         }
     }
     // k of group s of thread t in stage i, (t + T s) mod Ns, written so that
@@ -510,20 +521,30 @@ struct TeamFFT {
                     }
                 };
                 if constexpr (Lds::kSeq) {
-                    // one chain at a time through a one-chain buffer
+                    // G chains at a time through a G-chain buffer
                     constexpr int R2 = radix(I + 1);
+                    constexpr int G = Lds::kGroup;
+                    static_assert(NC % G == 0, "the chains split into whole groups");
 #pragma unroll
-                    for (int c = 0; c < NC; ++c) {
+                    for (int c0 = 0; c0 < NC; c0 += G) {
                         lds.sync();
 #pragma unroll
                         for (int e = 0; e < E; ++e) {
                             int base, off;
                             put_at(e, base, off);
-                            lds.put1(base, off, d[c][e]);
+                            cx<Real> v[G];
+#pragma unroll
+                            for (int g = 0; g < G; ++g) v[g] = d[c0 + g][e];
+                            lds.putg(base, off, v);
                         }
                         lds.sync();
 #pragma unroll
-                        for (int e = 0; e < E; ++e) d[c][e] = lds.get1(t, T * (e / R2) + (e % R2) * (N / R2));
+                        for (int e = 0; e < E; ++e) {
+                            cx<Real> v[G];
+                            lds.getg(t, T * (e / R2) + (e % R2) * (N / R2), v);
+#pragma unroll
+                            for (int g = 0; g < G; ++g) d[c0 + g][e] = v[g];
+                        }
                     }
                 } else {
                     lds.sync();
@@ -590,40 +611,57 @@ struct LdsCols {
     __device__ __forceinline__ void sync() { __syncthreads(); }
 };
 
-// Strided passes, two chains per line stored side by side: element-major,
-// column next, chain fastest, so one 16-byte (FP32) access moves both chains.
-template <class Real>
-struct LdsCols2 {
+// Strided passes, NC chains per line: element-major, column next, chain
+// fastest, so one wide access moves two chains of an element (two FP32
+// chains: 16 bytes).  Four chains live in two such planes (chains 0-1, then
+// 2-3), so that consecutive positions stay one 2-chain row apart and the
+// lanes of a wave spread over the LDS banks as with two chains.
+template <class Real, int NC>
+struct LdsColsN {
+    static_assert(NC == 1 || NC == 2 || NC == 4, "one, two or four chains");
     static constexpr bool kSeq = false;
+    static constexpr int kPlane = NC == 4 ? 2 : NC;  // chains per plane
     cx<Real>* buf;
     int stride;  // columns per element row
     int col;
-    __device__ __forceinline__ void put(int pos, const cx<Real> (&v)[2]) {
-        cx<Real>* q = buf + 2 * (pos * stride + col);
-        q[0] = v[0];
-        q[1] = v[1];
+    int plane = 0;  // elements per plane (four chains: positions * stride * 2)
+    __device__ __forceinline__ void put(int pos, const cx<Real> (&v)[NC]) {
+        cx<Real>* q = buf + kPlane * (pos * stride + col);
+#pragma unroll
+        for (int c = 0; c < NC; ++c) q[(c / kPlane) * plane + c % kPlane] = v[c];
     }
-    __device__ __forceinline__ void get(int pos, cx<Real> (&v)[2]) const {
-        const cx<Real>* q = buf + 2 * (pos * stride + col);
-        v[0] = q[0];
-        v[1] = q[1];
+    __device__ __forceinline__ void get(int pos, cx<Real> (&v)[NC]) const {
+        const cx<Real>* q = buf + kPlane * (pos * stride + col);
+#pragma unroll
+        for (int c = 0; c < NC; ++c) v[c] = q[(c / kPlane) * plane + c % kPlane];
     }
-    __device__ __forceinline__ void put2(int base, int off, const cx<Real> (&v)[2]) { put(base + off, v); }
-    __device__ __forceinline__ void get2(int base, int off, cx<Real> (&v)[2]) const { get(base + off, v); }
+    __device__ __forceinline__ void put2(int base, int off, const cx<Real> (&v)[NC]) { put(base + off, v); }
+    __device__ __forceinline__ void get2(int base, int off, cx<Real> (&v)[NC]) const { get(base + off, v); }
     __device__ __forceinline__ void sync() { __syncthreads(); }
 };
-
-// Strided passes, two chains per line exchanged one after the other through a
-// one-chain buffer: half the LDS of LdsCols2 per column, two more barriers per
-// exchange.
 template <class Real>
+using LdsCols2 = LdsColsN<Real, 2>;
+
+// Strided passes, the chains of a line exchanged G at a time through a
+// G-chain buffer: less LDS per column than all chains at once, two more
+// barriers per exchange for each further group.
+template <class Real, int G = 1>
 struct LdsColsSeq {
     static constexpr bool kSeq = true;
+    static constexpr int kGroup = G;
     cx<Real>* buf;
     int stride;  // columns per element row
     int col;
-    __device__ __forceinline__ void put1(int base, int off, cx<Real> v) { buf[(base + off) * stride + col] = v; }
-    __device__ __forceinline__ cx<Real> get1(int base, int off) const { return buf[(base + off) * stride + col]; }
+    __device__ __forceinline__ void putg(int base, int off, const cx<Real> (&v)[G]) {
+        cx<Real>* q = buf + G * ((base + off) * stride + col);
+#pragma unroll
+        for (int c = 0; c < G; ++c) q[c] = v[c];
+    }
+    __device__ __forceinline__ void getg(int base, int off, cx<Real> (&v)[G]) const {
+        const cx<Real>* q = buf + G * ((base + off) * stride + col);
+#pragma unroll
+        for (int c = 0; c < G; ++c) v[c] = q[c];
+    }
     __device__ __forceinline__ void sync() { __syncthreads(); }
 };
 
@@ -704,6 +742,7 @@ __device__ __forceinline__ float gld(const float* p) { return *(const PSN_GLOBAL
 __device__ __forceinline__ double gld(const double* p) { return *(const PSN_GLOBAL double*)(p); }
 // two consecutive complex floats in one 16-byte access (p 16-byte aligned)
 typedef float psn_f4 __attribute__((ext_vector_type(4)));
+typedef uint32_t psn_u2 __attribute__((ext_vector_type(2)));
 __device__ __forceinline__ void gst2(cx<float>* p, cx<float> a, cx<float> b) {
     *(PSN_GLOBAL psn_f4*)(p) = psn_f4{a.x, a.y, b.x, b.y};
 }
@@ -744,6 +783,20 @@ struct Work<DT_F32> {
     }
     // elements i and i+1 (i even)
     __device__ __forceinline__ void st2(size_t i, cx<float> a, cx<float> b) const { gst2(p + i, a, b); }
+    // elements ub + off and ub + off + 1 (ub + off even) in one 16-byte access
+    __device__ __forceinline__ void ld_pair(size_t ub, uint32_t off, cx<float>& a, cx<float>& b) const {
+        const psn_f4 v = *(const PSN_GLOBAL psn_f4*)(byte_off(sbase(p + ub), off * 8u));
+        a = {v.x, v.y};
+        b = {v.z, v.w};
+    }
+    __device__ __forceinline__ void st_pair(size_t ub, uint32_t off, cx<float> a, cx<float> b) const {
+        *(PSN_GLOBAL psn_f4*)(byte_off(sbase(p + ub), off * 8u)) = psn_f4{a.x, a.y, b.x, b.y};
+    }
+    __device__ __forceinline__ void ld_pair(size_t i, cx<float>& a, cx<float>& b) const {
+        const psn_f4 v = *(const PSN_GLOBAL psn_f4*)(p + i);
+        a = {v.x, v.y};
+        b = {v.z, v.w};
+    }
 };
 template <>
 struct Work<DT_F64> {
@@ -759,6 +812,20 @@ struct Work<DT_F64> {
     __device__ __forceinline__ void st2(size_t i, cx<double> a, cx<double> b) const {
         gst(p + i, a);
         gst(p + i + 1, b);
+    }
+    __device__ __forceinline__ void ld_pair(size_t ub, uint32_t off, cx<double>& a, cx<double>& b) const {
+        const cx<double>* q = byte_off(sbase(p + ub), off * 16u);
+        a = gld(q);
+        b = gld(q + 1);
+    }
+    __device__ __forceinline__ void st_pair(size_t ub, uint32_t off, cx<double> a, cx<double> b) const {
+        cx<double>* q = byte_off(sbase(p + ub), off * 16u);
+        gst(q, a);
+        gst(q + 1, b);
+    }
+    __device__ __forceinline__ void ld_pair(size_t i, cx<double>& a, cx<double>& b) const {
+        a = gld(p + i);
+        b = gld(p + i + 1);
     }
 };
 // FP32 high part + bfloat16 low part (two per 32-bit word): 6 bytes per real.
@@ -788,10 +855,29 @@ struct Work<DT_SPLIT> {
         gst(byte_off(sbase(lo + ub), off * 4u), low_of(v, h));
     }
     __device__ __forceinline__ void st2(size_t i, cx<double> a, cx<double> b) const {
-        st(i, a);
-        st(i + 1, b);
+        const cx<float> ha{float(a.x), float(a.y)}, hb{float(b.x), float(b.y)};
+        gst2(hi + i, ha, hb);
+        *(PSN_GLOBAL psn_u2*)(lo + i) = psn_u2{low_of(a, ha), low_of(b, hb)};
     }
-
+    // elements ub + off and ub + off + 1 (ub + off even): one 16-byte high
+    // access and one 8-byte low access
+    __device__ __forceinline__ void ld_pair(size_t ub, uint32_t off, cx<double>& a, cx<double>& b) const {
+        const psn_f4 h = *(const PSN_GLOBAL psn_f4*)(byte_off(sbase(hi + ub), off * 8u));
+        const psn_u2 l = *(const PSN_GLOBAL psn_u2*)(byte_off(sbase(lo + ub), off * 4u));
+        a = join({h.x, h.y}, l.x);
+        b = join({h.z, h.w}, l.y);
+    }
+    __device__ __forceinline__ void st_pair(size_t ub, uint32_t off, cx<double> a, cx<double> b) const {
+        const cx<float> ha{float(a.x), float(a.y)}, hb{float(b.x), float(b.y)};
+        *(PSN_GLOBAL psn_f4*)(byte_off(sbase(hi + ub), off * 8u)) = psn_f4{ha.x, ha.y, hb.x, hb.y};
+        *(PSN_GLOBAL psn_u2*)(byte_off(sbase(lo + ub), off * 4u)) = psn_u2{low_of(a, ha), low_of(b, hb)};
+    }
+    __device__ __forceinline__ void ld_pair(size_t i, cx<double>& a, cx<double>& b) const {
+        const psn_f4 h = *(const PSN_GLOBAL psn_f4*)(hi + i);
+        const psn_u2 l = *(const PSN_GLOBAL psn_u2*)(lo + i);
+        a = join({h.x, h.y}, l.x);
+        b = join({h.z, h.w}, l.y);
+    }
 };
 
 }  // namespace psn

@@ -88,7 +88,14 @@ constexpr int pick_lines(int N, int T, int cxbytes) {
 // write and read runs of KB * BL contiguous elements, and the two workgroups
 // of the axis-0 pass that share a kernel row (k1 and M-k1) read the two halves
 // of the same 128-byte lines.  BL is the column tile of the axis-1 passes.
-template <int N, int BL>
+//
+// Paired form (PAIR): two consecutive i0 of a column sit next to each other,
+//   slot / KB * blk + (i0 / 2 * (N / BL) + k2 / BL) * (2 KB BL) + (slot % KB) * 2 BL + (k2 % BL) * 2 + i0 % 2,
+// so a slot row of a tile holds BL columns x 2 i0 (128 bytes in FP32), the
+// axis-0 pass reads one 16-byte pair per lane and whole rows per eight lanes,
+// and the axis-1 passes, each workgroup handling an i0 pair, move runs of
+// 2 KB BL elements.
+template <int N, int BL, bool PAIR = false>
 struct W2Index {
     static constexpr int KB = psn_host::w2_k1_block(N);
     static constexpr size_t blk = size_t(N) * N * KB + psn_host::kW2BlockPad;  // stride of k1 blocks
@@ -100,11 +107,28 @@ struct W2Index {
     }
     static __device__ __forceinline__ size_t at(int i0, int k1, int k2) {
         const int sl = slot(k1);
-        return size_t(sl / KB) * blk + (size_t(i0) * (N / BL) + k2 / BL) * size_t(KB * BL) + size_t(sl % KB) * BL +
-               k2 % BL;
+        if constexpr (PAIR) {
+            return size_t(sl / KB) * blk + (size_t(i0 >> 1) * (N / BL) + k2 / BL) * size_t(2 * KB * BL) +
+                   size_t(sl % KB) * (2 * BL) + (k2 % BL) * 2 + (i0 & 1);
+        } else {
+            return size_t(sl / KB) * blk + (size_t(i0) * (N / BL) + k2 / BL) * size_t(KB * BL) +
+                   size_t(sl % KB) * BL + k2 % BL;
+        }
     }
-    // stride between consecutive i0 at fixed (k1, k2)
-    static constexpr size_t s0 = size_t(N) * KB;
+    // stride between consecutive i0 (PAIR: consecutive i0 pairs) at fixed (k1, k2)
+    static constexpr size_t s0 = size_t(N) * KB * (PAIR ? 2 : 1);
+};
+
+// Sizes whose W2 is stored in the paired form.  The axis-0 pass then splits
+// each line by decimation in time into its even and odd samples, giving four
+// half-length chains per line; the axis-1 passes take an i0 pair per
+// workgroup.
+// FP32 only: the FP64-arithmetic precisions already move 16 bytes per lane
+// and element, and their paired axis-1 passes measured slower (one 144 KB
+// workgroup per CU then holds two lines per column).
+template <int N, int DT>
+struct PairW2 {
+    static constexpr bool value = DT == DT_F32 && N >= 16 && (N & (N - 1)) == 0;
 };
 
 // W1 layout, tiled over k2: element (i0, i1, k2) lives at
@@ -503,9 +527,8 @@ p3_col0(const Batch<DT> bt) {
     using Real = typename C::Real;
     using Ff = TeamFFT<N, C::T, Real, -1, false>;
     using Fi = TeamFFT<N, C::T, Real, +1, true>;
-    using WI = W2Index<N, Cfg<N, DT>::BS>;
+    using WI = W2Index<N, Cfg<N, DT>::BS, PairW2<N, DT>::value>;
     using G0 = Col0<N, DT>;
-    constexpr size_t s0 = WI::s0;
     extern __shared__ __align__(16) unsigned char smem[];
 
     if (int(blockIdx.x) >= bt.count * G0::groups) return;
@@ -524,13 +547,12 @@ p3_col0(const Batch<DT> bt) {
     const int k1 = set == 0 ? q : (q == 0 ? N : 2 * N - q);
     const int kt1 = (q == 0) ? (set ? N : 0) : q;
     const int partner = (q == 0) ? set : 1 - set;
-    const size_t base = WI::at(0, k1, 0);
     const typename C::Kt* Krow = K + psn_host::k_index(N, kt1, 0, 0);  // column 0 of plane kt1
     const typename C::Kt* Kbr = Kb + size_t(kt1) * (N + 1);
 
     cx<Real> x[Ff::E], acc[Ff::E];
 #pragma unroll
-    for (int e = 0; e < Ff::E; ++e) x[e] = w2.ld(base + size_t(Ff::in_pos(t, e)) * s0);
+    for (int e = 0; e < Ff::E; ++e) x[e] = w2.ld(WI::at(Ff::in_pos(t, e), k1, 0));
     LdsCols<Real> lds{sb + set, 2, 0};
 #pragma unroll
     for (int p = 0; p < 2; ++p) {
@@ -560,7 +582,7 @@ p3_col0(const Batch<DT> bt) {
     }
     if (live) {
 #pragma unroll
-        for (int e = 0; e < Ff::E; ++e) w2.st(base + size_t(Fi::out_pos(t, e)) * s0, acc[e]);
+        for (int e = 0; e < Ff::E; ++e) w2.st(WI::at(Fi::out_pos(t, e), k1, 0), acc[e]);
     }
 }
 
@@ -608,6 +630,304 @@ p4_inv(const Batch<DT> bt) {
 #pragma unroll
     for (int e = 0; e < E; ++e)
         w1.st(W1I::at(i0, F::out_pos(t, e), k2), twfma<+1>(d[1][e], w[e], d[0][e]));
+}
+
+// ------------------------------------------------------------------ paired W2
+// Axis-1 forward over an i0 pair: unit = (i0 pair, tile of B columns k2).
+// The two lines of each column (i0 = 2p and 2p + 1) are transformed one after
+// the other through the same LDS exchange area; the first one's outputs wait
+// in registers.  The outputs are then staged in LDS in the paired W2 order and
+// stored as whole runs of 2 KB B elements, one 16-byte (FP32) pair per lane.
+// Minimum waves per SIMD asked of the compiler for the paired axis-1 passes:
+// with up to 8 points per thread, two 512-thread workgroups per CU (the LDS
+// allows two) need at most 128 VGPRs.
+constexpr int p24p_waves(int e, bool seq) { return e > 8 ? 1 : (seq ? 3 : 4); }
+
+template <int N, int DT, int B, int TT, bool SEQ>
+__global__ void __launch_bounds__((B * TT), p24p_waves(N / TT, SEQ))
+p2p_fwd(const Batch<DT> bt) {
+    using C = Cfg<N, DT>;
+    using Real = typename C::Real;
+    using F = TeamFFT<N, TT, Real, -1, false>;
+    using WI = W2Index<N, C::BS, true>;
+    static_assert(B == C::BS, "the axis-1 tile is the W2 layout tile");
+    constexpr int E = F::E;
+    constexpr int tiles = N / B;
+    constexpr int units = (N / 2) * tiles;  // per problem
+    extern __shared__ __align__(16) unsigned char smem[];
+    cx<Real>* sb = reinterpret_cast<cx<Real>*>(smem);
+    cx<Real>* stw = sb + (SEQ ? 1 : 2) * B * N;
+    const int ug = xcd_unit();
+    if (ug >= bt.count * units) return;
+    const Prob<DT>& P = bt.p[ug / units];
+    const Work<DT>& w1 = P.w1;
+    const Work<DT>& w2 = P.w2;
+    const cx<Real>* __restrict__ tw = P.tw;
+    const int u = ug % units;
+    const int pr = u / tiles, tile = u % tiles;
+    const int c = threadIdx.x % B, t = threadIdx.x / B;
+    const int k2 = tile * B + c;
+    using W1I = W1Index<N, B>;
+
+    cx<Real> xa[E], xb[E], w[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const int pos = F::in_pos(t, e);
+        xa[e] = w1.ld(W1I::at(2 * pr, pos, k2));
+        xb[e] = w1.ld(W1I::at(2 * pr + 1, pos, k2));
+        w[e] = tw[pos];
+    }
+    TwLds<Real> tl{stw};
+    tl.fill(tw, N, threadIdx.x, B * TT);  // visible after the first exchange
+    ChainLds<Real, SEQ> lds{sb, B, c};
+    cx<Real> ra[2][E], d[2][E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        ra[0][e] = xa[e];
+        ra[1][e] = xa[e] * w[e];
+    }
+    F::template run<2>(ra, t, tl, lds);
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        d[0][e] = xb[e];
+        d[1][e] = xb[e] * w[e];
+    }
+    F::template run<2>(d, t, tl, lds);
+    {
+        // Stage in rounds of HALF slots: element (slot, column, i0 parity) at
+        // ((slot - h HALF) B + c) 2 + parity, the order of the W2 runs.
+        constexpr int KB = WI::KB, RUN = 2 * KB * B;
+        constexpr int HALF = SEQ ? N / 2 : N;  // slots per round
+        static_assert((2 * HALF * B) % RUN == 0, "rounds cover whole runs");
+        const size_t tile0 = WI::at(2 * pr, 0, tile * B);  // start of block 0's run
+#pragma unroll
+        for (int h = 0; h < 2 * N / HALF; ++h) {
+            __syncthreads();  // the last exchange's (or round's) reads are done
+#pragma unroll
+            for (int e = 0; e < E; ++e) {
+                const int m = F::out_pos(t, e);
+#pragma unroll
+                for (int ch = 0; ch < 2; ++ch) {
+                    const int sl = WI::slot(2 * m + ch) - h * HALF;
+                    if (sl >= 0 && sl < HALF) {
+                        sb[(sl * B + c) * 2] = ra[ch][e];
+                        sb[(sl * B + c) * 2 + 1] = d[ch][e];
+                    }
+                }
+            }
+            __syncthreads();
+            for (int g = 2 * int(threadIdx.x); g < 2 * HALF * B; g += 2 * B * TT) {
+                const int gg = h * 2 * HALF * B + g;
+                w2.st2(tile0 + size_t(gg / RUN) * WI::blk + gg % RUN, sb[g], sb[g + 1]);
+            }
+        }
+    }
+}
+
+// Axis-0 pass on the paired layout.  One workgroup = SL rows of W2 (k1 and
+// M-k1 when SL = 2) and B adjacent columns.  A line x (n samples along i0)
+// is split by decimation in time: with w = exp(-2 pi i / 2n) and H = n/2,
+//   A = DFT_H(x[2i]),  B = DFT_H(x[2i+1]),
+//   C = DFT_H(x[2i] w^2i),  D = DFT_H(x[2i+1] w^(2i+1)),
+// and the padded forward transform is X[2m] = A[m] + w^2m B[m],
+// X[2m + 2H] = A[m] - w^2m B[m] (likewise X[2m+1], X[2m+1+2H] from C and D).
+// After the multiply by K, the inverse that keeps the first n samples splits
+// by decimation in frequency into four half-length inverses whose inputs are
+// P = ks A + kd w^2m B and Q = ks B + kd w^-2m A (ks, kd = sum and difference
+// of the kernel values of the two outputs) for the even outputs (likewise R,
+// S for the odd ones); then u[2i] = P[i] + w^-2i R[i] and
+// u[2i+1] = Q[i] + w^-(2i+1) S[i].  Each lane loads and stores the pair
+// (x[2i], x[2i+1]) of its column as one access; all four chains advance in
+// lockstep, G of them per LDS exchange round.  Column 0 is left to p3_col0.
+// Per-stage twiddle rows for the half-length transforms of the paired middle
+// pass (n >= 512, where the saved index arithmetic outweighs the fill).
+template <int N>
+struct P3PRows {
+    static constexpr bool value = N >= 512;
+};
+template <int N, int DT, int TT>
+constexpr size_t p3p_tw_entries() {
+    using Real = typename Cfg<N, DT>::Real;
+    using Ff = TeamFFT<N / 2, TT, Real, -1, false>;
+    using Fi = TeamFFT<N / 2, TT, Real, +1, true>;
+    if constexpr (P3PRows<N>::value) return Ff::rows_size() + (Ff::template same_rows<Fi>() ? 0 : Fi::rows_size());
+    else return TwLds<Real>::slots(N);
+}
+
+template <int N, int DT, int B, int TT, int SL, int G>
+__global__ void __launch_bounds__((B * TT * SL), (G < 4 && DT == DT_F32 ? 2 : 1))
+p3p_conv(const Batch<DT> bt) {
+    using C = Cfg<N, DT>;
+    using Real = typename C::Real;
+    constexpr int H = N / 2;
+    using Ff = TeamFFT<H, TT, Real, -1, false>;
+    using Fi = TeamFFT<H, TT, Real, +1, true>;
+    static_assert(SL == 1 || SL == 2, "one row or a row pair per workgroup");
+    static_assert(G == 4 || G == 2, "four chains exchanged all at once or two at a time");
+    constexpr int E = Ff::E;
+    constexpr int tiles = N / B;
+    constexpr int units = (2 / SL) * N * tiles;  // per problem
+    using WI = W2Index<N, C::BS, true>;
+    static_assert(C::BS % B == 0, "the axis-0 tile lies inside a W2 layout tile");
+    constexpr size_t sp = WI::s0;  // stride of i0 pairs in W2
+    extern __shared__ __align__(16) unsigned char smem[];
+    cx<Real>* sb = reinterpret_cast<cx<Real>*>(smem);
+    cx<Real>* stw = sb + size_t(G) * H * B * SL;
+
+    const int ug = xcd_unit();
+    if (ug >= bt.count * units) return;  // whole workgroup
+    const Prob<DT>& P = bt.p[ug / units];
+    const Work<DT>& w2 = P.w2;
+    const typename C::Kt* __restrict__ K = P.K;
+    const cx<Real>* __restrict__ tw = P.tw;
+    const int u = ug % units;
+    int q, tile, set;
+    if constexpr (SL == 1) {
+        const int item = u >> 1;
+        set = u & 1;
+        q = item / tiles;
+        tile = item % tiles;
+    } else {
+        q = u / tiles;
+        tile = u % tiles;
+        set = (threadIdx.x / B) & 1;
+    }
+    const int c = threadIdx.x % B, t = threadIdx.x / (B * SL);
+    const int k2 = tile * B + c;
+    static_assert(WI::s0 * H * sizeof(cx<double>) < (size_t(1) << 32) &&
+                      size_t(N + 1) * (N + 1) * N * sizeof(double) < (size_t(1) << 32),
+                  "lane byte offsets fit 32 bits");
+    // pair i = in_pos(t, e) of row q (set 0) or M-q (set 1, 2 BS elements on)
+    const size_t ub = WI::at(0, q, tile * B);
+    const uint32_t xl = uint32_t(2 * c) + uint32_t(set) * (2 * C::BS) + uint32_t(t) * uint32_t(sp);
+    auto xb = [&](int e) { return ub + size_t(Ff::in_pos(0, e)) * sp; };
+
+    cx<Real> d[4][E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) w2.ld_pair(xb(e), xl, d[0][e], d[1][e]);
+    // kernel values of outputs 2m, 2m+1 (m = out_pos(t, e) = t + m0) and of
+    // their partners n - 2m, n - 2m - 1: a uniform base plus one of two lane
+    // offsets in the tiled K row (plane q, or n for the set-1 row of pair 0)
+    constexpr int KT = psn_host::k_tile(N);
+    using Kt = typename C::Kt;
+    const uint32_t kl = uint32_t(psn_host::k_index(N, (set != 0 && q == 0) ? N : q, 0, k2));
+    const uint32_t kup = (kl + uint32_t(2 * t * KT)) * uint32_t(sizeof(Kt));
+    const uint32_t kdn = (kl + uint32_t(2 * (TT - 1 - t) * KT)) * uint32_t(sizeof(Kt));
+    auto kv = [&](int e, int odd, int mirror) -> Real {
+        const int m0 = Ff::out_pos(0, e);
+        if (!mirror) return Real(gld(byte_off(sbase(K + (2 * m0 + odd) * KT), kup)));
+        return Real(gld(byte_off(sbase(K + (N - 2 * m0 - odd - 2 * (TT - 1)) * KT), kdn)));
+    };
+    // Stage twiddles of the half-length transforms: per-stage rows for
+    // n >= 512 (filled from every other entry of the 2n table), else the
+    // swizzled 2n table read at even entries.
+    constexpr bool kRows = P3PRows<N>::value;
+    TwLds<Real> tl{stw};
+    cx<Real>* rows_i = stw + (Ff::template same_rows<Fi>() ? 0 : Ff::rows_size());
+    if constexpr (kRows) {
+        Ff::template fill_rows<1, 2>(stw, tw, threadIdx.x, B * TT * SL);  // visible after the first exchange
+        if constexpr (!Ff::template same_rows<Fi>()) Fi::template fill_rows<1, 2>(rows_i, tw, threadIdx.x, B * TT * SL);
+    } else {
+        tl.fill(tw, N, threadIdx.x, B * TT * SL);   // visible after the first exchange
+        if constexpr (Ff::S == 1) __syncthreads();  // no exchange: the combine reads the table
+    }
+    // pre-twiddles w^2i, w^(2i+1) of the pair this lane holds
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const int i = Ff::in_pos(t, e);
+        d[2][e] = d[0][e] * gld(tw + 2 * i);
+        d[3][e] = d[1][e] * gld(tw + 2 * i + 1);
+    }
+    using Lds = std::conditional_t<G == 4, LdsColsN<Real, 4>, LdsColsSeq<Real, 2>>;
+    Lds lds{sb, B * SL, int(threadIdx.x % (B * SL))};
+    if constexpr (G == 4) lds.plane = 2 * H * B * SL;
+    TwHalf<Real> th{tl};
+    if constexpr (kRows) Ff::template run<4>(d, t, TwRows<Real>{stw}, lds);
+    else Ff::template run<4>(d, t, th, lds);
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const int m = Ff::out_pos(t, e);
+        // w^2m = exp(-2 pi i m / n)
+        const cx<Real> W = kRows ? gld(byte_off(sbase(tw + 2 * Ff::out_pos(0, e)), uint32_t(2 * t * C::CX)))
+                                 : tl(2 * m);
+#pragma unroll
+        for (int odd = 0; odd < 2; ++odd) {
+            const Real k0 = kv(e, odd, 0), k1 = kv(e, odd, 1);
+            const Real ks = k0 + k1, kd = k0 - k1;
+            const cx<Real> a = d[2 * odd][e], b = d[2 * odd + 1][e];
+            // P = ks a + (kd W) b,  Q = ks b + conj(kd W) a
+            const cx<Real> kw = scale(W, kd);
+            d[2 * odd][e] = {fmad(ks, a.x, fmad(kw.x, b.x, -kw.y * b.y)), fmad(ks, a.y, fmad(kw.x, b.y, kw.y * b.x))};
+            d[2 * odd + 1][e] = {fmad(ks, b.x, fmad(kw.x, a.x, kw.y * a.y)), fmad(ks, b.y, fmad(kw.x, a.y, -kw.y * a.x))};
+        }
+    }
+    if constexpr (kRows) Fi::template run<4>(d, t, TwRows<Real>{rows_i}, lds);
+    else Fi::template run<4>(d, t, th, lds);
+    if (k2 != 0) {
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const int i = Fi::out_pos(t, e);
+            const cx<Real> u0 = twfma<+1>(d[2][e], gld(tw + 2 * i), d[0][e]);
+            const cx<Real> u1 = twfma<+1>(d[3][e], gld(tw + 2 * i + 1), d[1][e]);
+            w2.st_pair(xb(e), xl, u0, u1);
+        }
+    }
+}
+
+// Axis-1 inverse over an i0 pair: unit = (i0 pair, tile of B columns k2).
+// Each lane loads rows 2j and 2j+1 of its column as (i0 = 2p, 2p + 1) pairs;
+// the two lines are inverted one after the other and combined as
+// y = y_even + w^-j y_odd.
+template <int N, int DT, int B, int TT, bool SEQ>
+__global__ void __launch_bounds__((B * TT), p24p_waves(N / TT, SEQ))
+p4p_inv(const Batch<DT> bt) {
+    using C = Cfg<N, DT>;
+    using Real = typename C::Real;
+    using F = TeamFFT<N, TT, Real, +1, false>;
+    using WI = W2Index<N, C::BS, true>;
+    static_assert(B == C::BS, "the axis-1 tile is the W2 layout tile");
+    constexpr int E = F::E;
+    constexpr int tiles = N / B;
+    constexpr int units = (N / 2) * tiles;  // per problem
+    extern __shared__ __align__(16) unsigned char smem[];
+    cx<Real>* sb = reinterpret_cast<cx<Real>*>(smem);
+    cx<Real>* stw = sb + (SEQ ? 1 : 2) * B * N;
+    const int ug = xcd_unit();
+    if (ug >= bt.count * units) return;
+    const Prob<DT>& P = bt.p[ug / units];
+    const Work<DT>& w1 = P.w1;
+    const Work<DT>& w2 = P.w2;
+    const cx<Real>* __restrict__ tw = P.tw;
+    const int u = ug % units;
+    const int pr = u / tiles, tile = u % tiles;
+    const int c = threadIdx.x % B, t = threadIdx.x / B;
+    const int k2 = tile * B + c;
+    using W1I = W1Index<N, B>;
+
+    cx<Real> a[2][E], b[2][E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const int pos = F::in_pos(t, e);
+        w2.ld_pair(WI::at(2 * pr, 2 * pos, k2), a[0][e], b[0][e]);
+        w2.ld_pair(WI::at(2 * pr, 2 * pos + 1, k2), a[1][e], b[1][e]);
+    }
+    TwLds<Real> tl{stw};
+    tl.fill(tw, N, threadIdx.x, B * TT);  // visible after the first exchange
+    if constexpr (F::S == 1) __syncthreads();  // no exchange: the combine reads the table
+    ChainLds<Real, SEQ> lds{sb, B, c};
+    // the combine twiddles w^-j come from the LDS table (fewer live registers)
+    F::template run<2>(a, t, tl, lds);
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const int j = F::out_pos(t, e);
+        w1.st(W1I::at(2 * pr, j, k2), twfma<+1>(a[1][e], tl(j), a[0][e]));
+    }
+    F::template run<2>(b, t, tl, lds);
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const int j = F::out_pos(t, e);
+        w1.st(W1I::at(2 * pr + 1, j, k2), twfma<+1>(b[1][e], tl(j), b[0][e]));
+    }
 }
 
 // ------------------------------------------------------------------ P5
@@ -737,6 +1057,39 @@ struct Sched {
     static_assert(tile_ok(N, d24, C::CX) && tile_ok(N, d3, C::CX), "default tiles must fit");
 };
 
+// Axis-0 tiles on the paired layout: B columns, TT threads per half line
+// (n/2 points), SL rows per workgroup, G chains per LDS exchange round.
+struct TileP {
+    int B, TT;
+    int SL = 1;
+    int G = 4;
+};
+
+constexpr bool tilep_ok(int N, TileP v, int cxbytes) {
+    return v.B >= 1 && v.TT >= 1 && (v.SL == 1 || v.SL == 2) && (v.G == 2 || v.G == 4) && N % v.B == 0 &&
+           (N / 2) % v.TT == 0 && v.B * v.TT * v.SL <= 1024 &&
+           (size_t(v.G) * (N / 2) * v.B * v.SL + ((2 * N + 15) & ~15)) * cxbytes <= size_t(kMaxLdsP3) &&
+           make_plan(N / 2, N / 2 / v.TT).n > 0 && N / 2 / v.TT <= 16;
+}
+constexpr TileP pick_tilep(int N, TileP v, TileP dflt, int cxbytes, int layout_tile) {
+    return (tilep_ok(N, v, cxbytes) && layout_tile % v.B == 0) ? v : dflt;
+}
+
+template <int N, int DT>
+struct SchedP {
+    using C = Cfg<N, DT>;
+    static constexpr int H = N / 2;
+    static constexpr int e8 = H >= 8 ? 8 : H;
+    static constexpr int e4 = H >= 4 ? 4 : H;
+    // eight points per chain and thread, two chains per exchange round (all
+    // four at once halves the workgroups per CU and measured 45 % slower at
+    // n = 512); the row pair k1, M-k1 per workgroup; four points per chain
+    // (twice the threads, one more exchange)
+    static constexpr TileP d3{C::BP3, H / e8, 1, 2};
+    static constexpr TileP v3[3] = {d3, pick_tilep(N, TileP{C::BP3, H / e8, 2, 2}, d3, C::CX, C::BS),
+                                    pick_tilep(N, TileP{C::BP3, H / e4, 1, 2}, d3, C::CX, C::BS)};
+};
+
 // LDS of the strided passes: the exchange area plus the stage twiddle rows
 template <int N, int DT, int B, int TT, bool SEQ>
 constexpr size_t lds_p24() {
@@ -786,21 +1139,74 @@ hipError_t launch_p3(const Batch<DT>& bt, hipStream_t s) {
     return hipSuccess;
 }
 
+// the axis-1 passes on the paired layout: the same tiles, one i0 pair per workgroup
+template <int N, int DT, int I>
+hipError_t launch_p2p(const Batch<DT>& bt, hipStream_t s) {
+    constexpr TileV v = Sched<N, DT>::v24[I];
+    const size_t lds = lds_p24<N, DT, v.B, v.TT, v.SEQ>();
+    static const bool ok = allow_lds(reinterpret_cast<const void*>(&p2p_fwd<N, DT, v.B, v.TT, v.SEQ>), lds);
+    if (!ok) return hipErrorInvalidConfiguration;
+    hipLaunchKernelGGL((p2p_fwd<N, DT, v.B, v.TT, v.SEQ>), dim3(xcd_grid(long(bt.count) * (N / 2) * (N / v.B))),
+                       dim3(v.B * v.TT), lds, s, bt);
+    return hipSuccess;
+}
+
+template <int N, int DT, int I>
+hipError_t launch_p4p(const Batch<DT>& bt, hipStream_t s) {
+    constexpr TileV v = Sched<N, DT>::v24[I];
+    const size_t lds = lds_p24<N, DT, v.B, v.TT, v.SEQ>();
+    static const bool ok = allow_lds(reinterpret_cast<const void*>(&p4p_inv<N, DT, v.B, v.TT, v.SEQ>), lds);
+    if (!ok) return hipErrorInvalidConfiguration;
+    hipLaunchKernelGGL((p4p_inv<N, DT, v.B, v.TT, v.SEQ>), dim3(xcd_grid(long(bt.count) * (N / 2) * (N / v.B))),
+                       dim3(v.B * v.TT), lds, s, bt);
+    return hipSuccess;
+}
+
+template <int N, int DT, int I>
+hipError_t launch_p3p(const Batch<DT>& bt, hipStream_t s) {
+    constexpr TileP v = SchedP<N, DT>::v3[I];
+    static_assert(tilep_ok(N, v, Cfg<N, DT>::CX), "paired axis-0 tile must fit");
+    const size_t lds = (size_t(v.G) * (N / 2) * v.B * v.SL + p3p_tw_entries<N, DT, v.TT>()) * Cfg<N, DT>::CX;
+    static const bool ok =
+        allow_lds(reinterpret_cast<const void*>(&p3p_conv<N, DT, v.B, v.TT, v.SL, v.G>), lds);
+    if (!ok) return hipErrorInvalidConfiguration;
+    hipLaunchKernelGGL((p3p_conv<N, DT, v.B, v.TT, v.SL, v.G>),
+                       dim3(xcd_grid(long(bt.count) * (2 / v.SL) * N * (N / v.B))), dim3(v.B * v.TT * v.SL), lds,
+                       s, bt);
+    return hipSuccess;
+}
+
 template <int N, int DT>
 hipError_t launch_p24(const Batch<DT>& bt, hipStream_t s, int v, bool forward) {
-    switch (v) {
-        case 1: return forward ? launch_p2<N, DT, 1>(bt, s) : launch_p4<N, DT, 1>(bt, s);
-        case 2: return forward ? launch_p2<N, DT, 2>(bt, s) : launch_p4<N, DT, 2>(bt, s);
-        default: return forward ? launch_p2<N, DT, 0>(bt, s) : launch_p4<N, DT, 0>(bt, s);
+    if constexpr (PairW2<N, DT>::value) {
+        switch (v) {
+            case 1: return forward ? launch_p2p<N, DT, 1>(bt, s) : launch_p4p<N, DT, 1>(bt, s);
+            case 2: return forward ? launch_p2p<N, DT, 2>(bt, s) : launch_p4p<N, DT, 2>(bt, s);
+            default: return forward ? launch_p2p<N, DT, 0>(bt, s) : launch_p4p<N, DT, 0>(bt, s);
+        }
+    } else {
+        switch (v) {
+            case 1: return forward ? launch_p2<N, DT, 1>(bt, s) : launch_p4<N, DT, 1>(bt, s);
+            case 2: return forward ? launch_p2<N, DT, 2>(bt, s) : launch_p4<N, DT, 2>(bt, s);
+            default: return forward ? launch_p2<N, DT, 0>(bt, s) : launch_p4<N, DT, 0>(bt, s);
+        }
     }
 }
 
 template <int N, int DT>
 hipError_t launch_p3v(const Batch<DT>& bt, hipStream_t s, int v) {
-    switch (v) {
-        case 1: return launch_p3<N, DT, 1>(bt, s);
-        case 2: return launch_p3<N, DT, 2>(bt, s);
-        default: return launch_p3<N, DT, 0>(bt, s);
+    if constexpr (PairW2<N, DT>::value) {
+        switch (v) {
+            case 1: return launch_p3p<N, DT, 1>(bt, s);
+            case 2: return launch_p3p<N, DT, 2>(bt, s);
+            default: return launch_p3p<N, DT, 0>(bt, s);
+        }
+    } else {
+        switch (v) {
+            case 1: return launch_p3<N, DT, 1>(bt, s);
+            case 2: return launch_p3<N, DT, 2>(bt, s);
+            default: return launch_p3<N, DT, 0>(bt, s);
+        }
     }
 }
 

@@ -101,14 +101,23 @@ def team_fft(x, n, t_count, sign, rev):
 
 
 def _cases():
+    seen = set()
     for n in compiled_sizes():
         es = {elems_per_thread(n, 4), elems_per_thread(n, 8)}
         odd = n // (n & -n)
         if odd > 1:
             es.add(2 * odd)  # the half-length candidate of the axis-1 passes
         for e in sorted(es):
-            if n % e == 0:
+            if n % e == 0 and (n, e) not in seen:
+                seen.add((n, e))
                 yield n, e
+        if n >= 16 and odd == 1:
+            # the half-length chains of the middle pass on the paired layout
+            h = n // 2
+            for e in (min(8, h), min(4, h)):
+                if (h, e) not in seen:
+                    seen.add((h, e))
+                    yield h, e
 
 
 @pytest.mark.parametrize("n,e", list(_cases()))
@@ -166,3 +175,65 @@ def test_prime_factor_index_maps(r1, r2):
                 out[(r2 * t1 * k1 + r1 * t2 * k2) % r] = b[k2]
         ref = np.fft.fft(x) if sign < 0 else np.fft.ifft(x) * r
         assert np.max(np.abs(out - ref)) <= 1e-12 * r
+
+
+@pytest.mark.parametrize("n", [16, 64, 512])
+def test_paired_middle_pass_split(n):
+    """The middle pass on the paired layout: a line x of n samples split by
+    decimation in time into four half-length chains (even and odd samples,
+    with and without the pre-twiddle w^j), joined by a radix-2 combine,
+    multiplied by the folded kernel through its sum and difference over the
+    two joined outputs, split again by decimation in frequency into four
+    half-length inverses, and recombined with w^-j.  The result must equal
+    the plain zero-padded length-2n convolution cropped to n samples (both
+    unnormalised)."""
+    rng = np.random.default_rng(n)
+    x = rng.standard_normal(n) + 1j * rng.standard_normal(n)
+    kfold = rng.standard_normal(n + 1)                     # K at folded index 0..n
+    k = np.arange(2 * n)
+    kfull = kfold[np.minimum(k, 2 * n - k)]
+    ref = (np.fft.ifft(kfull * np.fft.fft(x, 2 * n)) * 2 * n)[:n]
+
+    h = n // 2
+    w = np.exp(-2j * np.pi * np.arange(2 * n) / (2 * n))   # w^j, j < 2n
+    i = np.arange(h)
+    xe, xo = x[0::2], x[1::2]
+    A, B = np.fft.fft(xe), np.fft.fft(xo)
+    C, D = np.fft.fft(xe * w[2 * i]), np.fft.fft(xo * w[2 * i + 1])
+    m = np.arange(h)
+    W = w[2 * m]                                           # exp(-2 pi i m / n)
+    out = []
+    for a, b, odd in ((A, B, 0), (C, D, 1)):
+        k0, k1 = kfold[2 * m + odd], kfold[n - 2 * m - odd]
+        ks, kd = k0 + k1, k0 - k1
+        p = ks * a + kd * (W * b)
+        q = ks * b + kd * (np.conj(W) * a)
+        out.append((np.fft.ifft(p) * h, np.fft.ifft(q) * h))
+    (P, Q), (R, S) = out
+    u = np.empty(n, complex)
+    u[0::2] = P + np.conj(w[2 * i]) * R
+    u[1::2] = Q + np.conj(w[2 * i + 1]) * S
+    assert np.max(np.abs(u - ref)) <= 1e-12 * n * np.max(np.abs(ref))
+
+
+def test_paired_w2_index_is_a_permutation():
+    """The paired W2 layout maps every (i0, k1, k2) to its own element, keeps
+    each slot row of a tile (B columns x an i0 pair) contiguous, and puts the
+    two i0 of a column next to each other."""
+    n, bl = 16, 8
+    kb, m = 4, 2 * n                      # the k1 block of n = 16
+    blk = n * n * kb + 512
+
+    def slot(k1):
+        return 0 if k1 == 0 else 1 if k1 == n else (2 * k1 if k1 < n else 2 * (m - k1) + 1)
+
+    def at(i0, k1, k2):
+        sl = slot(k1)
+        return (sl // kb) * blk + ((i0 >> 1) * (n // bl) + k2 // bl) * (2 * kb * bl) + (sl % kb) * 2 * bl \
+            + (k2 % bl) * 2 + (i0 & 1)
+
+    idx = [at(i0, k1, k2) for i0 in range(n) for k1 in range(m) for k2 in range(n)]
+    assert len(set(idx)) == len(idx)
+    assert at(4, 3, 9) + 1 == at(5, 3, 9)
+    row = sorted(at(i0, 3, k2) for i0 in (6, 7) for k2 in range(8, 16))
+    assert row == list(range(row[0], row[0] + 16))
