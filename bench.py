@@ -196,6 +196,25 @@ def bench_size(psn, torch, np, n, steps, warmup, with_oracle):
     return out
 
 
+def kernel_build_times(psn, torch, n, reps=3):
+    """Wall time of psn_kernel_build (setup: mode integrals, correction
+    constants, octant assembly, workspace allocation) on the benchmark box."""
+    mix, desc = workload(n)
+    out = {"metric": "kernel build (setup) wall time", "unit": "ms", "workload": desc, "n": n}
+    torch.cuda.init()
+    for dt in ("f32", "f64"):
+        ts = []
+        for _ in range(reps):
+            t = time.perf_counter()
+            plan = psn.Plan(n, mix.box.b[0], 1e-12, dt).build()
+            torch.cuda.synchronize()
+            ts.append(1e3 * (time.perf_counter() - t))
+            del plan
+        out[f"{dt}_ms"] = ts
+        log(f"kernel build {dt}: " + ", ".join(f"{v:.1f}" for v in ts) + " ms")
+    return out
+
+
 def radix16_probe():
     """Radix-16 DFTs per second: VALU butterflies vs FP32 MFMA (built by build.py)."""
     import subprocess
@@ -225,6 +244,9 @@ def main():
     ap.add_argument("--no-compare", action="store_true", help="skip the FP64 and split paths")
     ap.add_argument("--no-batched", action="store_true", help="skip the mixed-size batched workload")
     ap.add_argument("--extra-n", type=int, default=256, help="second benchmark size (0 = none)")
+    ap.add_argument("--kernel-build", action="store_true",
+                    help="only time psn_kernel_build (the setup phase) for the benchmark box, FP32 and FP64, "
+                         "with the schedule autotuner off, and print one JSON line")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one 1 GiB device-to-device tensor copy (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -234,6 +256,8 @@ def main():
               file=sys.stderr)
         sys.exit(2)
 
+    if args.kernel_build:
+        os.environ["PSN_TUNE"] = "0"   # read by the library at build time
     import numpy as np
     import torch
 
@@ -241,6 +265,9 @@ def main():
     import workloads as W
 
     n = args.n
+    if args.kernel_build:
+        print(json.dumps(kernel_build_times(psn, torch, n)), flush=True)
+        return
     mix, desc = workload(n)
     L = mix.box.b[0]
     log(f"generating density n={n}")

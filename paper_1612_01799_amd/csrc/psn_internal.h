@@ -97,7 +97,9 @@ constexpr int kScheduleCandidates = 3;
 
 // Kernel spectrum build on the device (FP64), written into p->K / p->Kb in
 // the plan's storage type, plus C0/C2 into the two doubles at d_c.
-// d_A holds three tables of terms x (n+1) doubles (one per axis).
+// d_A is scratch of kbuild_scratch_doubles(n, terms) doubles: three mode
+// tables of terms x (n+1), three moment tables, and the k2 = n column.
+size_t kbuild_scratch_doubles(int n, int terms);
 hipError_t launch_kernel_build(psn_plan* p, const double* d_tau, const double* d_w, int terms,
                                const double* d_glx, const double* d_glw, double* d_A, double* d_c,
                                hipStream_t stream);

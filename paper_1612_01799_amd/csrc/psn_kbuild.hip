@@ -5,12 +5,22 @@
 //   C0, C2   = int_{B_delta} (U - U_GS) dy,  int_{B_delta} |y|^2 (U - U_GS) dy
 //   K(k)     = sum_j w_j a_j(k0) a_j(k1) a_j(k2) + C0 - (C2/6) |kappa|^2
 //
-// The mode integrals use the Gaussian's Fourier transform where the tail
-// beyond T is below exp(-37) (tau T >= 6.1) and composite 16-point
-// Gauss-Legendre elsewhere, with one panel per half period of the highest
-// frequency plus eight; for tau T < 1 the integrand is split into cos(kappa y)
-// (integral exactly 2T at k = 0 and 0 otherwise, since kappa T = pi k) plus the
-// smooth remainder expm1(-tau^2 y^2) cos(kappa y).
+// Mode integrals, by the size of tau T:
+// * tau T >= 6.1: the Gaussian's Fourier transform (the tail beyond T is
+//   below exp(-37) relative).
+// * tau T < 1: the integrand is 1 plus expm1(-tau^2 y^2) = sum_{m>=1}
+//   (-tau^2 y^2)^m / m!, so a_j(k) = 2T [k = 0] + sum_m (-tau_j^2)^m / m! M_m(k)
+//   with the moments M_m(k) = 2 int_0^T y^2m cos(kappa_k y) dy, which do not
+//   depend on the term.  Each summand is at most 2T (tau T)^2m / (m! (2m+1)),
+//   so the series converges without cancellation; the moments are computed
+//   once per frequency by composite 16-point Gauss-Legendre.
+// * otherwise: composite 16-point Gauss-Legendre of the integral itself, with
+//   one panel per two half periods of cos(kappa_k y) plus eight.
+// The octant assembly is the product of the (k0, k1) rows sum_j over the
+// terms with the (k2) columns: a register-tiled FP64 GEMM.  On a cube the
+// three axes share one mode table and K is symmetric in (k0, k1); then only
+// k0 <= k1 is computed, the pair product a_j(k0) a_j(k1) is formed first (so
+// both halves agree bitwise) and each value is written to both places.
 #include "psn_device.h"
 #include "psn_internal.h"
 
@@ -18,8 +28,72 @@ namespace psn {
 
 constexpr double kPi = 3.14159265358979323846;
 
+constexpr int kMoments = 22;  // series terms of the tau T < 1 branch: 1/22! < 1e-21
+
+// Panels of the composite Gauss-Legendre rule for frequency k: one per two
+// half periods of cos(kappa_k y) on [0, T] plus eight.
+__device__ __forceinline__ int gl_panels(int k) { return (k + 1) / 2 + 8; }
+
+// Sum over the kPanelThreads threads of a workgroup, in a fixed order (the
+// result does not depend on timing); v[] holds each thread's NV partial sums;
+// red has NV * kPanelThreads doubles; the sums land in v[] of thread 0.
+constexpr int kPanelThreads = 64;
+template <int NV>
+__device__ __forceinline__ void block_sum(double (&v)[NV], double* red) {
+    const int tid = threadIdx.x;
+#pragma unroll
+    for (int m = 0; m < NV; ++m) red[m * kPanelThreads + tid] = v[m];
+    __syncthreads();
+    for (int h = kPanelThreads / 2; h > 0; h >>= 1) {
+        if (tid < h) {
+#pragma unroll
+            for (int m = 0; m < NV; ++m) red[m * kPanelThreads + tid] += red[m * kPanelThreads + tid + h];
+        }
+        __syncthreads();
+    }
+    if (tid == 0) {
+#pragma unroll
+        for (int m = 0; m < NV; ++m) v[m] = red[m * kPanelThreads];
+    }
+}
+
+// M_m(k) = 2 int_0^T y^2m cos(kappa_k y) dy, m = 1..kMoments, for k = 0..n;
+// Mom[(m - 1) (n + 1) + k].  One workgroup per k; its threads share the panels.
+__global__ void __launch_bounds__(kPanelThreads) k_moments(int n, double T, double period,
+                                                           const double* __restrict__ glx,
+                                                           const double* __restrict__ glw, double* __restrict__ Mom) {
+    __shared__ double red[kMoments * kPanelThreads];
+    const int k = blockIdx.x;
+    const double kap = 2.0 * kPi * double(k) / period;
+    const int panels = gl_panels(k);
+    const double half = 0.5 * T / panels;
+    double acc[kMoments];
+#pragma unroll
+    for (int m = 0; m < kMoments; ++m) acc[m] = 0.0;
+    for (int pnl = threadIdx.x; pnl < panels; pnl += kPanelThreads) {
+        const double mid = (2 * pnl + 1) * half;
+        for (int g = 0; g < 16; ++g) {
+            const double y = mid + half * glx[g];
+            const double y2 = y * y;
+            double f = 2.0 * half * glw[g] * cos(kap * y);
+#pragma unroll
+            for (int m = 0; m < kMoments; ++m) {
+                f *= y2;
+                acc[m] += f;
+            }
+        }
+    }
+    block_sum(acc, red);
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int m = 0; m < kMoments; ++m) Mom[size_t(m) * (n + 1) + k] = acc[m];
+    }
+}
+
+// Terms with tau T >= 6.1 (closed form) or tau T < 1 (moment series); the
+// terms in between are left to k_modes_mid.  One thread per (k, j).
 __global__ void k_modes(const double* __restrict__ tau, int n, double T, double period,
-                        const double* __restrict__ glx, const double* __restrict__ glw, double* __restrict__ A) {
+                        const double* __restrict__ Mom, double* __restrict__ A) {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
     const int j = blockIdx.y;
     if (k > n) return;
@@ -29,26 +103,48 @@ __global__ void k_modes(const double* __restrict__ tau, int n, double T, double 
     double a;
     if (tT >= 6.1) {
         a = sqrt(kPi) / t * exp(-kap * kap / (4.0 * t * t));
-    } else {
-        const bool small = tT < 1.0;
-        const int panels = n / 2 + 8;
-        const double half = 0.5 * T / panels;
-        double sum = 0.0;
-        for (int pnl = 0; pnl < panels; ++pnl) {
-            const double mid = (2 * pnl + 1) * half;
-            double ps = 0.0;
-#pragma unroll
-            for (int g = 0; g < 16; ++g) {
-                const double y = mid + half * glx[g];
-                const double ty = t * y;
-                const double f = small ? expm1(-ty * ty) : exp(-ty * ty);
-                ps += glw[g] * f * cos(kap * y);
-            }
-            sum += half * ps;
+    } else if (tT < 1.0) {
+        // 2T [k = 0] + sum_m (-tau^2)^m / m! M_m(k), smallest terms first
+        double c[kMoments];
+        double cm = 1.0;
+        for (int m = 0; m < kMoments; ++m) {
+            cm *= -t * t / double(m + 1);
+            c[m] = cm;
         }
-        a = 2.0 * sum + ((small && k == 0) ? 2.0 * T : 0.0);
+        double sum = 0.0;
+        for (int m = kMoments - 1; m >= 0; --m) sum = fma(c[m], Mom[size_t(m) * (n + 1) + k], sum);
+        a = sum + (k == 0 ? 2.0 * T : 0.0);
+    } else {
+        return;
     }
     A[size_t(j) * (n + 1) + k] = a;
+}
+
+// Terms with 1 <= tau T < 6.1, by composite Gauss-Legendre: one workgroup
+// per (k, term), its threads share the panels.
+__global__ void __launch_bounds__(kPanelThreads) k_modes_mid(const double* __restrict__ tau, int j0, int n, double T,
+                                                             double period, const double* __restrict__ glx,
+                                                             const double* __restrict__ glw, double* __restrict__ A) {
+    __shared__ double red[kPanelThreads];
+    const int k = blockIdx.x, j = j0 + blockIdx.y;
+    const double t = tau[j];
+    const double kap = 2.0 * kPi * double(k) / period;
+    const int panels = gl_panels(k);
+    const double half = 0.5 * T / panels;
+    double sum[1] = {0.0};
+    for (int pnl = threadIdx.x; pnl < panels; pnl += kPanelThreads) {
+        const double mid = (2 * pnl + 1) * half;
+        double ps = 0.0;
+#pragma unroll
+        for (int g = 0; g < 16; ++g) {
+            const double y = mid + half * glx[g];
+            const double ty = t * y;
+            ps += glw[g] * exp(-ty * ty) * cos(kap * y);
+        }
+        sum[0] += half * ps;
+    }
+    block_sum(sum, red);
+    if (threadIdx.x == 0) A[size_t(j) * (n + 1) + k] = 2.0 * sum[0];
 }
 
 // int_0^delta r^p exp(-tau^2 r^2) dr for p = 2, 4
@@ -99,35 +195,100 @@ __global__ void k_correction(const double* __restrict__ tau, const double* __res
     }
 }
 
-// One workgroup per (k0~, k1~); threads run over k2 = 0..n.  A0, A1, A2 are the
-// mode tables of the three axes (the same table for a cube).
-template <class Kt>
-__global__ void k_assemble(const double* __restrict__ A0, const double* __restrict__ A1,
-                           const double* __restrict__ A2, const double* __restrict__ w, int terms, int n,
-                           double p0, double p1, double p2, const double* __restrict__ Cc, double scale,
-                           Kt* __restrict__ K, Kt* __restrict__ Kb) {
-    extern __shared__ double cj[];
-    __shared__ double edge[2];
-    const int kt0 = blockIdx.x, kt1 = blockIdx.y;
+// K(k0, k1, n) for every (k0, k1), FP64: the k2 = n column, which the
+// octant stores folded with k2 = 0.  Kn[k1 (n + 1) + k0].
+__global__ void k_edge(const double* __restrict__ A0, const double* __restrict__ A1, const double* __restrict__ A2,
+                       const double* __restrict__ w, int terms, int n, double p0, double p1, double p2,
+                       const double* __restrict__ Cc, double* __restrict__ Kn) {
+    const int k0 = blockIdx.x * blockDim.x + threadIdx.x, k1 = blockIdx.y;
+    if (k0 > n) return;
     const int np1 = n + 1;
-    for (int j = threadIdx.x; j < terms; j += blockDim.x)
-        cj[j] = w[j] * A0[size_t(j) * np1 + kt0] * A1[size_t(j) * np1 + kt1];
-    __syncthreads();
-    const double C0 = Cc[0], C2 = Cc[1];
-    const double b0 = 2.0 * kPi * kt0 / p0, b1 = 2.0 * kPi * kt1 / p1, b2 = 2.0 * kPi / p2;
-    const double q01 = b0 * b0 + b1 * b1;
-    for (int k2 = threadIdx.x; k2 <= n; k2 += blockDim.x) {
-        double s = 0.0;
-        for (int j = 0; j < terms; ++j) s = fma(cj[j], A2[size_t(j) * np1 + k2], s);
-        const double v = s + C0 - (C2 / 6.0) * (q01 + b2 * b2 * double(k2) * k2);
-        if (k2 == 0) edge[0] = v;
-        else if (k2 == n) edge[1] = v;
-        else K[psn_host::k_index(n, kt1, kt0, k2)] = Kt(scale * v);
+    double s = 0.0;
+    for (int j = 0; j < terms; ++j)
+        s = fma(A0[size_t(j) * np1 + k0] * A1[size_t(j) * np1 + k1], w[j] * A2[size_t(j) * np1 + n], s);
+    const double b0 = 2.0 * kPi * k0 / p0, b1 = 2.0 * kPi * k1 / p1, b2 = 2.0 * kPi * n / p2;
+    Kn[size_t(k1) * np1 + k0] = s + Cc[0] - (Cc[1] / 6.0) * (b0 * b0 + b1 * b1 + b2 * b2);
+}
+
+// Octant assembly, k2 = 0..n-1: a workgroup of 256 threads computes a tile of
+// 128 k0 x 64 k2 of one k1 plane, each thread 4 k0 x 8 k2 (k0 = k0b + r +
+// 32 i, k2 = k2b + q + 8 c with q = tid % 8, r = tid / 8), so that the eight
+// lanes of a k0 row write 8 consecutive k2 of the tiled octant.  The terms
+// stream through LDS in chunks of 16: a_j(k0) and w_j a_j(k2).  With SYM
+// (A0 == A1) only tiles with k0b <= k1 run and entries with k0 <= k1 are
+// written, to (k0, k1) and (k1, k0).
+constexpr int kTile0 = 128, kTile2 = 64, kChunk = 16;
+
+template <class Kt, bool SYM>
+__global__ void __launch_bounds__(256) k_gemm(const double* __restrict__ A0, const double* __restrict__ A1,
+                                              const double* __restrict__ A2, const double* __restrict__ w, int terms,
+                                              int n, double p0, double p1, double p2,
+                                              const double* __restrict__ Cc, const double* __restrict__ Kn,
+                                              double scale, Kt* __restrict__ K, Kt* __restrict__ Kb) {
+    __shared__ double sa[kChunk][kTile0], sb[kChunk][kTile2], s1[kChunk];
+    const int np1 = n + 1;
+    const int k1 = blockIdx.z;
+    const int k0b = blockIdx.y * kTile0, k2b = blockIdx.x * kTile2;
+    if (SYM && k0b > k1) return;  // whole workgroup: the mirror tile covers it
+    const int tid = threadIdx.x, q = tid % 8, r = tid / 8;
+    double acc[4][8];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int c = 0; c < 8; ++c) acc[i][c] = 0.0;
+    for (int j0 = 0; j0 < terms; j0 += kChunk) {
+        __syncthreads();  // the previous chunk's reads are done
+        for (int idx = tid; idx < kChunk * kTile0; idx += 256) {
+            const int jj = idx / kTile0, c = idx % kTile0, j = j0 + jj, k0 = k0b + c;
+            sa[jj][c] = (j < terms && k0 <= n) ? A0[size_t(j) * np1 + k0] : 0.0;
+        }
+        for (int idx = tid; idx < kChunk * kTile2; idx += 256) {
+            const int jj = idx / kTile2, c = idx % kTile2, j = j0 + jj, k2 = k2b + c;
+            sb[jj][c] = (j < terms && k2 < n) ? w[j] * A2[size_t(j) * np1 + k2] : 0.0;
+        }
+        if (tid < kChunk) s1[tid] = j0 + tid < terms ? A1[size_t(j0 + tid) * np1 + k1] : 0.0;
+        __syncthreads();
+#pragma unroll 2
+        for (int jj = 0; jj < kChunk; ++jj) {
+            const double a1 = s1[jj];
+            double p[4], b[8];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) p[i] = sa[jj][r + 32 * i] * a1;
+#pragma unroll
+            for (int c = 0; c < 8; ++c) b[c] = sb[jj][q + 8 * c];
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int c = 0; c < 8; ++c) acc[i][c] = fma(p[i], b[c], acc[i][c]);
+        }
     }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        K[psn_host::k_index(n, kt1, kt0, 0)] = Kt(scale * 0.5 * (edge[0] + edge[1]));
-        Kb[size_t(kt1) * np1 + kt0] = Kt(scale * 0.5 * (edge[0] - edge[1]));
+    const double C0 = Cc[0], C2 = Cc[1];
+    const double b1 = 2.0 * kPi * k1 / p1;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int k0 = k0b + r + 32 * i;
+        if (k0 > n || (SYM && k0 > k1)) continue;
+        const double b0 = 2.0 * kPi * k0 / p0;
+        const double q01 = b0 * b0 + b1 * b1;
+#pragma unroll
+        for (int c = 0; c < 8; ++c) {
+            const int k2 = k2b + q + 8 * c;
+            if (k2 >= n) continue;
+            const double b2 = 2.0 * kPi * k2 / p2;
+            const double v = acc[i][c] + C0 - (C2 / 6.0) * (q01 + b2 * b2);
+            if (k2 == 0) {
+                const double e = Kn[size_t(k1) * np1 + k0];
+                K[psn_host::k_index(n, k1, k0, 0)] = Kt(scale * 0.5 * (v + e));
+                Kb[size_t(k1) * np1 + k0] = Kt(scale * 0.5 * (v - e));
+                if (SYM && k0 != k1) {
+                    K[psn_host::k_index(n, k0, k1, 0)] = Kt(scale * 0.5 * (v + e));
+                    Kb[size_t(k0) * np1 + k1] = Kt(scale * 0.5 * (v - e));
+                }
+            } else {
+                K[psn_host::k_index(n, k1, k0, k2)] = Kt(scale * v);
+                if (SYM && k0 != k1) K[psn_host::k_index(n, k0, k1, k2)] = Kt(scale * v);
+            }
+        }
     }
 }
 
@@ -135,10 +296,18 @@ __global__ void k_assemble(const double* __restrict__ A0, const double* __restri
 
 namespace psn_host {
 
+size_t kbuild_scratch_doubles(int n, int terms) {
+    const size_t np1 = size_t(n) + 1;
+    return 3 * size_t(terms) * np1 + 3 * size_t(psn::kMoments) * np1 + np1 * np1;
+}
+
 hipError_t launch_kernel_build(psn_plan* p, const double* d_tau, const double* d_w, int terms, const double* d_glx,
                                const double* d_glw, double* d_A, double* d_c, hipStream_t s) {
     const int n = p->n;
-    const size_t tab = size_t(terms) * (n + 1);
+    const size_t np1 = size_t(n) + 1;
+    const size_t tab = size_t(terms) * np1;
+    double* d_mom = d_A + 3 * tab;                       // 3 x kMoments x (n+1)
+    double* d_kn = d_mom + 3 * size_t(psn::kMoments) * np1;  // (n+1)^2
     // one mode table per distinct axis length
     const double* A[3];
     for (int q = 0; q < 3; ++q) {
@@ -150,22 +319,43 @@ hipError_t launch_kernel_build(psn_plan* p, const double* d_tau, const double* d
             continue;
         }
         A[q] = d_A + q * tab;
+        double* mom = d_mom + q * size_t(psn::kMoments) * np1;
+        hipLaunchKernelGGL(psn::k_moments, dim3(n + 1), dim3(psn::kPanelThreads), 0, s, n, p->T[q], p->period[q],
+                           d_glx, d_glw, mom);
         hipLaunchKernelGGL(psn::k_modes, dim3((n + 1 + 127) / 128, terms), dim3(128), 0, s, d_tau, n, p->T[q],
-                           p->period[q], d_glx, d_glw, d_A + q * tab);
+                           p->period[q], mom, d_A + q * tab);
+        // the terms with 1 <= tau T < 6.1: a contiguous range (tau grows with j)
+        int j0 = terms, j1 = 0;
+        for (int j = 0; j < terms; ++j) {
+            const double tT = p->tau[j] * p->T[q];
+            if (tT >= 1.0 && tT < 6.1) {
+                j0 = j < j0 ? j : j0;
+                j1 = j + 1;
+            }
+        }
+        if (j1 > j0)
+            hipLaunchKernelGGL(psn::k_modes_mid, dim3(n + 1, j1 - j0), dim3(psn::kPanelThreads), 0, s, d_tau, j0, n,
+                               p->T[q], p->period[q], d_glx, d_glw, d_A + q * tab);
     }
     hipLaunchKernelGGL(psn::k_correction, dim3(1), dim3(256), 0, s, d_tau, d_w, terms, p->delta, d_c);
+    hipLaunchKernelGGL(psn::k_edge, dim3((n + 1 + 127) / 128, n + 1), dim3(128), 0, s, A[0], A[1], A[2], d_w, terms,
+                       n, p->period[0], p->period[1], p->period[2], d_c, d_kn);
     const double M = 2.0 * n;
     const double scale = 1.0 / (M * M * M);
-    const size_t lds = size_t(terms) * sizeof(double);
+    const bool sym = A[0] == A[1];
+    const dim3 grid((n + psn::kTile2 - 1) / psn::kTile2, (n + 1 + psn::kTile0 - 1) / psn::kTile0, n + 1);
+#define PSN_GEMM(KT, SYMV)                                                                                         \
+    hipLaunchKernelGGL((psn::k_gemm<KT, SYMV>), grid, dim3(256), 0, s, A[0], A[1], A[2], d_w, terms, n,            \
+                       p->period[0], p->period[1], p->period[2], d_c, d_kn, scale, static_cast<KT*>(p->K),         \
+                       static_cast<KT*>(p->Kb))
     if (p->dtype == PSN_F32) {
-        hipLaunchKernelGGL(psn::k_assemble<float>, dim3(n + 1, n + 1), dim3(256), lds, s, A[0], A[1], A[2], d_w,
-                           terms, n, p->period[0], p->period[1], p->period[2], d_c, scale, static_cast<float*>(p->K),
-                           static_cast<float*>(p->Kb));
+        if (sym) PSN_GEMM(float, true);
+        else PSN_GEMM(float, false);
     } else {
-        hipLaunchKernelGGL(psn::k_assemble<double>, dim3(n + 1, n + 1), dim3(256), lds, s, A[0], A[1], A[2], d_w,
-                           terms, n, p->period[0], p->period[1], p->period[2], d_c, scale,
-                           static_cast<double*>(p->K), static_cast<double*>(p->Kb));
+        if (sym) PSN_GEMM(double, true);
+        else PSN_GEMM(double, false);
     }
+#undef PSN_GEMM
     return hipGetLastError();
 }
 

@@ -440,7 +440,7 @@ psn_status psn_kernel_build(psn_plan* p, void* stream) {
 
     DevBuf d_tau, d_w, d_gl, d_A, d_c;
     if ((st = dev_alloc(&d_tau.p, terms * 8, &tot)) || (st = dev_alloc(&d_w.p, terms * 8, &tot)) ||
-        (st = dev_alloc(&d_gl.p, 32 * 8, &tot)) || (st = dev_alloc(&d_A.p, 3 * size_t(terms) * (n + 1) * 8, &tot)) ||
+        (st = dev_alloc(&d_gl.p, 32 * 8, &tot)) || (st = dev_alloc(&d_A.p, psn_host::kbuild_scratch_doubles(p->n, terms) * 8, &tot)) ||
         (st = dev_alloc(&d_c.p, 2 * 8, &tot))) {
         free_device(p);
         return st;
