@@ -13,6 +13,8 @@ in numpy/scipy, written step by step from the paper:
 * ``correction`` near-zone correction constants C0, C2 from the Taylor expansion (section 2)
 * ``kernel``     kernel spectrum K = G-tensor + C0 - C2/6 |kappa|^2 (section 2)
 * ``solve``      zero-padded FFT convolution and the error metric E (sections 2, 5)
+* ``paper_form`` the correction by the paper's route: Laplacian from the
+                 finite Fourier series of the density, an N-size FFT pair (sections 2-3)
 * ``direct``     brute-force direct summation of the same discrete convolution
 * ``analytic``   the paper's closed-form potentials for its test densities (section 5)
 
@@ -25,8 +27,10 @@ from .modes import mode_integrals
 from .correction import correction
 from .kernel import KernelSpectrum, kernel_spectrum, half_spectrum
 from .solve import solve, error_E
+from .paper_form import laplacian_fourier, solve_paper_form
 from . import analytic, direct
 
 __all__ = ["Geometry", "geometry", "gaussian_sum", "mode_integrals", "correction",
            "KernelSpectrum", "kernel_spectrum", "half_spectrum", "solve", "error_E",
+           "laplacian_fourier", "solve_paper_form",
            "analytic", "direct"]
