@@ -43,6 +43,19 @@ typedef struct psn_plan psn_plan;
  *             real); FP64 kernel spectrum; FP64 input and output. */
 typedef enum { PSN_F64 = 0, PSN_F32 = 1, PSN_SPLIT = 2 } psn_dtype;
 
+/* How the near-zone correction I_delta ~ C0 rho + (C2/6) Laplace(rho) enters
+ * (paper section 2, eq. approx and the Taylor expansion that follows it).
+ *   PSN_CORRECTION_FOLDED   its symbol C0 - (C2/6)|kappa|^2 is added to the
+ *                           padded kernel spectrum: no extra work per solve.
+ *   PSN_CORRECTION_FOURIER  the paper's own route: the Laplacian from the
+ *                           finite Fourier series of the density on its
+ *                           n-point grid (period n h per axis), one forward
+ *                           and one backward FFT of size N = n^3 (section 3),
+ *                           added after the padded convolution with the
+ *                           G-tensor alone.
+ * For a resolved density the two agree to rounding. */
+typedef enum { PSN_CORRECTION_FOLDED = 0, PSN_CORRECTION_FOURIER = 1 } psn_correction;
+
 typedef enum {
     PSN_OK = 0,
     PSN_EINVAL = -1,  /* bad argument: null pointer, L <= 0, tol outside [1e-15, 1e-4], bad dtype */
@@ -77,6 +90,7 @@ typedef struct {
     int schedule[2];    /* tile candidates of the axis-1 passes and of the axis-0 pass */
     int tuned;          /* 1 if the schedule came from the autotuner (or its cache file) */
     int device;         /* HIP device the kernel spectrum was built on; -1 before the build */
+    int correction;     /* psn_correction */
 } psn_plan_info;
 
 /* Create a plan for an n^3 grid on [-L, L]^3 (the solver construction of the
@@ -166,6 +180,13 @@ psn_status psn_solve_timed(psn_plan *p, const void *rho, void *u, void *stream, 
  * candidate may run another radix plan or another order of operations.  For
  * one candidate the result is bitwise reproducible.  Errors: PSN_EINVAL. */
 psn_status psn_plan_set_schedule(psn_plan *p, int p24, int p3);
+
+/* Choose how the near-zone correction enters (psn_correction); call before
+ * psn_kernel_build, since the kernel spectrum differs.  With
+ * PSN_CORRECTION_FOURIER a solve also runs the size-N transform pair; its
+ * workspace is the plan's (or the batch entry's) own.
+ * Errors: PSN_EINVAL (bad mode), PSN_ESTATE (already built). */
+psn_status psn_plan_set_correction(psn_plan *p, int mode);
 
 /* Fill *info: the discretisation and error-control parameters of the paper's
  * sections 2-3 as this plan derived them (grid spacing h from the section 4

@@ -18,12 +18,15 @@ import ctypes
 import os
 
 __all__ = ["Plan", "PsnError", "solve_batched", "solve_batched_noalloc", "size_supported", "library_path",
-           "F64", "F32", "SPLIT", "STATUS"]
+           "F64", "F32", "SPLIT", "CORRECTION_FOLDED", "CORRECTION_FOURIER", "STATUS"]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "libpsn.so")
 
 F64, F32, SPLIT = 0, 1, 2
+CORRECTION_FOLDED, CORRECTION_FOURIER = 0, 1
+_CORRECTIONS = {"folded": CORRECTION_FOLDED, "fourier": CORRECTION_FOURIER,
+                CORRECTION_FOLDED: CORRECTION_FOLDED, CORRECTION_FOURIER: CORRECTION_FOURIER}
 _DTYPES = {"f64": F64, "f32": F32, "split": SPLIT, F64: F64, F32: F32, SPLIT: SPLIT}
 STATUS = {0: "PSN_OK", -1: "PSN_EINVAL", -2: "PSN_ESIZE", -3: "PSN_ENOMEM", -4: "PSN_EDEVICE",
           -5: "PSN_ESTATE", -6: "PSN_EFIT", -7: "PSN_ELIMIT"}
@@ -46,7 +49,7 @@ class PlanInfo(ctypes.Structure):
         ("C2", ctypes.c_double), ("built", ctypes.c_int), ("device_bytes", ctypes.c_size_t),
         ("algorithmic_bytes", ctypes.c_double), ("a", ctypes.c_double * 3), ("b", ctypes.c_double * 3),
         ("h3", ctypes.c_double * 3), ("T3", ctypes.c_double * 3), ("schedule", ctypes.c_int * 2),
-        ("tuned", ctypes.c_int), ("device", ctypes.c_int),
+        ("tuned", ctypes.c_int), ("device", ctypes.c_int), ("correction", ctypes.c_int),
     ]
 
 
@@ -79,6 +82,7 @@ def _load():
                                              ctypes.c_int, ctypes.POINTER(ctypes.c_int)]),
         "psn_kernel_download": (ctypes.c_int, [P, ctypes.POINTER(ctypes.c_double)]),
         "psn_plan_set_schedule": (ctypes.c_int, [P, ctypes.c_int, ctypes.c_int]),
+        "psn_plan_set_correction": (ctypes.c_int, [P, ctypes.c_int]),
         "psn_plan_destroy": (None, [P]),
         "psn_strerror": (ctypes.c_char_p, [ctypes.c_int]),
         "psn_last_error": (ctypes.c_char_p, []),
@@ -116,9 +120,13 @@ def _stream_handle(stream):
 
 class Plan:
     """One grid geometry: n^3 points on [-L, L]^3 (or on the box a..b when
-    `box=(a, b)` is given, a and b 3-sequences), Gaussian-sum tolerance tol."""
+    `box=(a, b)` is given, a and b 3-sequences), Gaussian-sum tolerance tol.
+    `correction` is "folded" (the near-zone correction's symbol added to the
+    kernel spectrum) or "fourier" (added after the convolution, with the
+    Laplacian from the density's size-N Fourier series)."""
 
-    def __init__(self, n: int, L: float = None, tol: float = 1e-12, dtype="f32", box=None):
+    def __init__(self, n: int, L: float = None, tol: float = 1e-12, dtype="f32", box=None,
+                 correction="folded"):
         self._h = ctypes.c_void_p()
         self.n = int(n)
         self.dtype = _DTYPES[dtype]
@@ -132,6 +140,8 @@ class Plan:
             self.L = max(0.5 * (b[q] - a[q]) for q in range(3))
             _check(_lib.psn_plan_create_box(self.n, a, b, float(tol), self.dtype, ctypes.byref(self._h)),
                    "psn_plan_create_box")
+        if _CORRECTIONS[correction] != CORRECTION_FOLDED:
+            _check(_lib.psn_plan_set_correction(self._h, _CORRECTIONS[correction]), "psn_plan_set_correction")
 
     # -- setup
     def build(self, stream=None) -> "Plan":

@@ -38,6 +38,8 @@ struct psn_plan {
     // schedule of the strided passes (candidate indices, see Sched)
     int sched24 = 0, sched3 = 0;
     bool tuned = false;
+    // near-zone correction: folded into K, or added by its Fourier series
+    int correction = PSN_CORRECTION_FOLDED;
 };
 
 namespace psn {

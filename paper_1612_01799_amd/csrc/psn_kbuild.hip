@@ -199,7 +199,7 @@ __global__ void k_correction(const double* __restrict__ tau, const double* __res
 // octant stores folded with k2 = 0.  Kn[k1 (n + 1) + k0].
 __global__ void k_edge(const double* __restrict__ A0, const double* __restrict__ A1, const double* __restrict__ A2,
                        const double* __restrict__ w, int terms, int n, double p0, double p1, double p2,
-                       const double* __restrict__ Cc, double* __restrict__ Kn) {
+                       const double* __restrict__ Cc, double fold, double* __restrict__ Kn) {
     const int k0 = blockIdx.x * blockDim.x + threadIdx.x, k1 = blockIdx.y;
     if (k0 > n) return;
     const int np1 = n + 1;
@@ -207,7 +207,7 @@ __global__ void k_edge(const double* __restrict__ A0, const double* __restrict__
     for (int j = 0; j < terms; ++j)
         s = fma(A0[size_t(j) * np1 + k0] * A1[size_t(j) * np1 + k1], w[j] * A2[size_t(j) * np1 + n], s);
     const double b0 = 2.0 * kPi * k0 / p0, b1 = 2.0 * kPi * k1 / p1, b2 = 2.0 * kPi * n / p2;
-    Kn[size_t(k1) * np1 + k0] = s + Cc[0] - (Cc[1] / 6.0) * (b0 * b0 + b1 * b1 + b2 * b2);
+    Kn[size_t(k1) * np1 + k0] = s + fold * (Cc[0] - (Cc[1] / 6.0) * (b0 * b0 + b1 * b1 + b2 * b2));
 }
 
 // Octant assembly, k2 = 0..n-1: a workgroup of 256 threads computes a tile of
@@ -223,8 +223,9 @@ template <class Kt, bool SYM>
 __global__ void __launch_bounds__(256) k_gemm(const double* __restrict__ A0, const double* __restrict__ A1,
                                               const double* __restrict__ A2, const double* __restrict__ w, int terms,
                                               int n, double p0, double p1, double p2,
-                                              const double* __restrict__ Cc, const double* __restrict__ Kn,
-                                              double scale, Kt* __restrict__ K, Kt* __restrict__ Kb) {
+                                              const double* __restrict__ Cc, double fold,
+                                              const double* __restrict__ Kn, double scale, Kt* __restrict__ K,
+                                              Kt* __restrict__ Kb) {
     __shared__ double sa[kChunk][kTile0], sb[kChunk][kTile2], s1[kChunk];
     const int np1 = n + 1;
     const int k1 = blockIdx.z;
@@ -275,7 +276,7 @@ __global__ void __launch_bounds__(256) k_gemm(const double* __restrict__ A0, con
             const int k2 = k2b + q + 8 * c;
             if (k2 >= n) continue;
             const double b2 = 2.0 * kPi * k2 / p2;
-            const double v = acc[i][c] + C0 - (C2 / 6.0) * (q01 + b2 * b2);
+            const double v = acc[i][c] + fold * (C0 - (C2 / 6.0) * (q01 + b2 * b2));
             if (k2 == 0) {
                 const double e = Kn[size_t(k1) * np1 + k0];
                 K[psn_host::k_index(n, k1, k0, 0)] = Kt(scale * 0.5 * (v + e));
@@ -338,15 +339,18 @@ hipError_t launch_kernel_build(psn_plan* p, const double* d_tau, const double* d
                                p->T[q], p->period[q], d_glx, d_glw, d_A + q * tab);
     }
     hipLaunchKernelGGL(psn::k_correction, dim3(1), dim3(256), 0, s, d_tau, d_w, terms, p->delta, d_c);
+    // the correction symbol is folded into K unless the plan adds it by the
+    // Fourier series of the density (then fold = 0 leaves the G-tensor alone)
+    const double fold = p->correction == PSN_CORRECTION_FOURIER ? 0.0 : 1.0;
     hipLaunchKernelGGL(psn::k_edge, dim3((n + 1 + 127) / 128, n + 1), dim3(128), 0, s, A[0], A[1], A[2], d_w, terms,
-                       n, p->period[0], p->period[1], p->period[2], d_c, d_kn);
+                       n, p->period[0], p->period[1], p->period[2], d_c, fold, d_kn);
     const double M = 2.0 * n;
     const double scale = 1.0 / (M * M * M);
     const bool sym = A[0] == A[1];
     const dim3 grid((n + psn::kTile2 - 1) / psn::kTile2, (n + 1 + psn::kTile0 - 1) / psn::kTile0, n + 1);
 #define PSN_GEMM(KT, SYMV)                                                                                         \
     hipLaunchKernelGGL((psn::k_gemm<KT, SYMV>), grid, dim3(256), 0, s, A[0], A[1], A[2], d_w, terms, n,            \
-                       p->period[0], p->period[1], p->period[2], d_c, d_kn, scale, static_cast<KT*>(p->K),         \
+                       p->period[0], p->period[1], p->period[2], d_c, fold, d_kn, scale, static_cast<KT*>(p->K),   \
                        static_cast<KT*>(p->Kb))
     if (p->dtype == PSN_F32) {
         if (sym) PSN_GEMM(float, true);

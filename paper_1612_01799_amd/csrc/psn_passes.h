@@ -1002,6 +1002,157 @@ p5_c2r(const Batch<DT> bt) {
     }
 }
 
+// ------------------------------------------------------------------ Fourier-series correction
+// The near-zone correction by the paper's own route (section 2: derivatives
+// from the finite Fourier series of the density, one forward and one
+// backward FFT of size N = n^3, section 3): z = C0 rho + (C2/6) Laplace_N(rho),
+// with the Laplacian's symbol -sum_q kappa_q^2, kappa_q = 2 pi k / (n h_q) at
+// the signed index k (period n h_q, the samples' own grid).  It runs after
+// the axis-1 inverse, while rho is intact (also in place) and W2 is free: z
+// lives in W2's memory, as n^3 complex values in C order, and is added to u
+// after the axis-2 pass.
+template <int DT>
+struct CorrProb {
+    const typename Prec<DT>::Io* rho;
+    typename Prec<DT>::Io* u;
+    cx<typename Prec<DT>::Real>* z;
+    const cx<typename Prec<DT>::Real>* tw;
+    double c0, c2;   // C0 and C2 / 6
+    double kq[3];    // 2 pi / (n h_q)
+};
+template <int DT>
+struct CorrBatch {
+    int count;
+    CorrProb<DT> p[kMaxBatch];
+};
+
+// z = rho + 0i (elementwise; blockIdx.y = problem)
+template <int N, int DT>
+__global__ void corr_load(const CorrBatch<DT> cb) {
+    const CorrProb<DT>& P = cb.p[blockIdx.y];
+    using Real = typename Prec<DT>::Real;
+    constexpr size_t n3 = size_t(N) * N * N;
+    for (size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n3; i += size_t(gridDim.x) * blockDim.x)
+        gst(P.z + i, cx<Real>{Real(P.rho[i]), Real(0)});
+}
+
+// z *= (C0 - (C2/6) |kappa|^2) / n^3
+template <int N, int DT>
+__global__ void corr_symbol(const CorrBatch<DT> cb) {
+    const CorrProb<DT>& P = cb.p[blockIdx.y];
+    using Real = typename Prec<DT>::Real;
+    constexpr size_t n3 = size_t(N) * N * N;
+    const double inv = 1.0 / double(n3);
+    for (size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n3; i += size_t(gridDim.x) * blockDim.x) {
+        const int k[3] = {int(i / (size_t(N) * N)), int((i / N) % N), int(i % N)};
+        double q = 0.0;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            const double kap = P.kq[a] * double(k[a] <= N / 2 ? k[a] : k[a] - N);
+            q += kap * kap;
+        }
+        const Real f = Real((P.c0 - P.c2 * q) * inv);
+        gst(P.z + i, scale(gld(P.z + i), f));
+    }
+}
+
+// u += Re z
+template <int N, int DT>
+__global__ void corr_add(const CorrBatch<DT> cb) {
+    const CorrProb<DT>& P = cb.p[blockIdx.y];
+    using Io = typename Prec<DT>::Io;
+    constexpr size_t n3 = size_t(N) * N * N;
+    for (size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n3; i += size_t(gridDim.x) * blockDim.x)
+        P.u[i] = Io(P.u[i] + Io(gld(P.z + i).x));
+}
+
+// Length-N transforms of z along axis AX (DIR = -1 forward, +1 inverse,
+// unnormalised).  Axis 2: a workgroup holds LC contiguous lines, one LDS row
+// each.  Axes 0 and 1: a workgroup holds B adjacent lines (consecutive i2),
+// element-major in LDS, so each point's B values are one contiguous run.
+template <int N, int DT>
+struct CorrCfg {
+    using Real = typename Prec<DT>::Real;
+    static constexpr int E = elems_per_thread(N, sizeof(Real));
+    static constexpr int T = N / E;
+    static constexpr int CX = sizeof(cx<Real>);
+    static constexpr int B = (N % 8 == 0 && (8 * N + TwLds<Real>::slots(N)) * CX <= 65536 && 8 * T <= 1024) ? 8
+                             : (N % 4 == 0 && (4 * N + TwLds<Real>::slots(N)) * CX <= 65536) ? 4
+                                                                                              : 1;
+    static constexpr int LC = Cfg<N, DT>::LC;
+    static constexpr int NP = Cfg<N, DT>::NP;
+};
+
+template <int N, int DT, int AX, int DIR>
+__global__ void corr_fft(const CorrBatch<DT> cb) {
+    using CC = CorrCfg<N, DT>;
+    using Real = typename CC::Real;
+    using F = TeamFFT<N, CC::T, Real, DIR, false>;
+    extern __shared__ __align__(16) unsigned char smem[];
+    cx<Real>* sb = reinterpret_cast<cx<Real>*>(smem);
+    const CorrProb<DT>& P = cb.p[blockIdx.y];
+    cx<Real>* __restrict__ z = P.z;
+    cx<Real> d[F::E];
+    if constexpr (AX == 2) {
+        const int t = threadIdx.x % CC::T, ln = threadIdx.x / CC::T;
+        const size_t base = (size_t(blockIdx.x) * CC::LC + ln) * N;
+        TwLds<Real> tl{sb + CC::LC * CC::NP};
+        tl.fill(P.tw, N, threadIdx.x, CC::LC * CC::T);
+        __syncthreads();
+#pragma unroll
+        for (int e = 0; e < F::E; ++e) d[e] = gld(z + base + F::in_pos(t, e));
+        LdsRows<Real> lds{sb + ln * CC::NP};
+        F::run1(d, t, tl, lds);
+#pragma unroll
+        for (int e = 0; e < F::E; ++e) gst(z + base + F::out_pos(t, e), d[e]);
+    } else {
+        constexpr int B = CC::B;
+        const int c = threadIdx.x % B, t = threadIdx.x / B;
+        const int line = blockIdx.x / (N / B), i2 = (blockIdx.x % (N / B)) * B + c;
+        // axis 1: (i0 = line, pos, i2); axis 0: (pos, i1 = line, i2)
+        const size_t stride = AX == 1 ? size_t(N) : size_t(N) * N;
+        const size_t base = (AX == 1 ? size_t(line) * N * N : size_t(line) * N) + i2;
+        TwLds<Real> tl{sb + B * N};
+        tl.fill(P.tw, N, threadIdx.x, B * CC::T);
+        __syncthreads();
+#pragma unroll
+        for (int e = 0; e < F::E; ++e) d[e] = gld(z + base + size_t(F::in_pos(t, e)) * stride);
+        LdsCols<Real> lds{sb, B, c};
+        F::run1(d, t, tl, lds);
+#pragma unroll
+        for (int e = 0; e < F::E; ++e) gst(z + base + size_t(F::out_pos(t, e)) * stride, d[e]);
+    }
+}
+
+template <int N, int DT>
+hipError_t launch_corr_fft_all(const CorrBatch<DT>& cb, hipStream_t s, bool forward) {
+    using CC = CorrCfg<N, DT>;
+    const size_t lds2 = (size_t(CC::LC) * CC::NP + TwLds<typename CC::Real>::slots(N)) * CC::CX;
+    const size_t lds01 = (size_t(CC::B) * N + TwLds<typename CC::Real>::slots(N)) * CC::CX;
+    const dim3 g2(N * N / CC::LC, cb.count), g01(N * (N / CC::B), cb.count);
+    const dim3 b2(CC::LC * CC::T), b01(CC::B * CC::T);
+    if (forward) {
+        hipLaunchKernelGGL((corr_fft<N, DT, 2, -1>), g2, b2, lds2, s, cb);
+        hipLaunchKernelGGL((corr_fft<N, DT, 1, -1>), g01, b01, lds01, s, cb);
+        hipLaunchKernelGGL((corr_fft<N, DT, 0, -1>), g01, b01, lds01, s, cb);
+    } else {
+        hipLaunchKernelGGL((corr_fft<N, DT, 0, +1>), g01, b01, lds01, s, cb);
+        hipLaunchKernelGGL((corr_fft<N, DT, 1, +1>), g01, b01, lds01, s, cb);
+        hipLaunchKernelGGL((corr_fft<N, DT, 2, +1>), g2, b2, lds2, s, cb);
+    }
+    return hipGetLastError();
+}
+
+template <int N, int DT>
+hipError_t launch_corr_z(const CorrBatch<DT>& cb, hipStream_t s) {
+    const dim3 g(1024, cb.count), b(256);
+    hipLaunchKernelGGL((corr_load<N, DT>), g, b, 0, s, cb);
+    hipError_t e = launch_corr_fft_all<N, DT>(cb, s, true);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((corr_symbol<N, DT>), g, b, 0, s, cb);
+    return launch_corr_fft_all<N, DT>(cb, s, false);
+}
+
 // ------------------------------------------------------------------ launcher
 // Kernels needing more than 64 KB of dynamic LDS must say so once.
 inline bool allow_lds(const void* fn, size_t bytes) {
@@ -1212,8 +1363,12 @@ hipError_t launch_p3v(const Batch<DT>& bt, hipStream_t s, int v) {
 
 // Enqueue the six kernels of one solve for bt.count problems of size N with
 // schedule (v24 for P2/P4, v3 for P3).
+// With cb (the entries whose plan adds the correction by its Fourier series),
+// z is formed after the axis-1 inverse and added after the axis-2 pass
+// (both counted in the last pass's event interval).
 template <int N, int DT>
-hipError_t solve_n(const Batch<DT>& bt, hipStream_t s, hipEvent_t* ev, int v24, int v3) {
+hipError_t solve_n(const Batch<DT>& bt, hipStream_t s, hipEvent_t* ev, int v24, int v3,
+                   const CorrBatch<DT>* cb = nullptr) {
     using C = Cfg<N, DT>;
     constexpr size_t tws = TwLds<typename C::Real>::slots(N);
     const size_t lds_rows = (size_t(C::LC) * C::NP + tws) * C::CX;
@@ -1233,7 +1388,9 @@ hipError_t solve_n(const Batch<DT>& bt, hipStream_t s, hipEvent_t* ev, int v24, 
     mark(3);
     if ((e = launch_p24<N, DT>(bt, s, v24, false)) != hipSuccess) return e;
     mark(4);
+    if (cb && (e = launch_corr_z<N, DT>(*cb, s)) != hipSuccess) return e;
     hipLaunchKernelGGL((p5_c2r<N, DT>), dim3(xcd_grid(cnt * N * N / C::LC)), dim3(C::LC * C::T), lds_rows, s, bt);
+    if (cb) hipLaunchKernelGGL((corr_add<N, DT>), dim3(1024, cb->count), dim3(256), 0, s, *cb);
     mark(5);
     return hipGetLastError();
 }
@@ -1304,18 +1461,40 @@ Prob<DT> prob_of(const psn_host::Slot& sl) {
     return pr;
 }
 
+template <int DT>
+CorrProb<DT> corr_of(const psn_host::Slot& sl) {
+    using Real = typename Prec<DT>::Real;
+    using Io = typename Prec<DT>::Io;
+    const psn_plan* p = sl.plan;
+    CorrProb<DT> c{};
+    c.rho = static_cast<const Io*>(sl.rho);
+    c.u = static_cast<Io*>(sl.u);
+    c.z = static_cast<cx<Real>*>(sl.W2);  // free between the axis-1 inverse and the end of the solve
+    c.tw = static_cast<const cx<Real>*>(p->tw);
+    c.c0 = p->C0;
+    c.c2 = p->C2 / 6.0;
+    for (int q = 0; q < 3; ++q) c.kq[q] = 2.0 * 3.14159265358979323846 / (double(p->n) * p->h[q]);
+    return c;
+}
+
 // Slots [0, count) share n, precision and schedule (the caller groups them so).
 template <int DT>
 hipError_t solve_group(const psn_host::Slot* slots, int count, hipStream_t s, hipEvent_t* ev) {
     const int v24 = slots[0].plan->sched24, v3 = slots[0].plan->sched3;
     for (int base = 0; base < count; base += kMaxBatch) {
         Batch<DT> bt{};
+        CorrBatch<DT> cb{};
         bt.count = count - base < kMaxBatch ? count - base : kMaxBatch;
-        for (int i = 0; i < bt.count; ++i) bt.p[i] = prob_of<DT>(slots[base + i]);
+        for (int i = 0; i < bt.count; ++i) {
+            const psn_host::Slot& sl = slots[base + i];
+            bt.p[i] = prob_of<DT>(sl);
+            if (sl.plan->correction == PSN_CORRECTION_FOURIER) cb.p[cb.count++] = corr_of<DT>(sl);
+        }
+        const CorrBatch<DT>* cbp = cb.count > 0 ? &cb : nullptr;
         hipError_t e = hipErrorInvalidValue;
         switch (slots[0].plan->n) {
 #define PSN_CASE(NN) \
-    case NN: e = solve_n<NN, DT>(bt, s, ev, v24, v3); break;
+    case NN: e = solve_n<NN, DT>(bt, s, ev, v24, v3, cbp); break;
             PSN_FOR_EACH_SIZE(PSN_CASE)
 #undef PSN_CASE
             default: break;

@@ -711,6 +711,7 @@ psn_status psn_plan_query(const psn_plan* p, psn_plan_info* info) {
     info->schedule[1] = p->sched3;
     info->tuned = p->tuned ? 1 : 0;
     info->device = p->built ? p->device : -1;
+    info->correction = p->correction;
     for (int q = 0; q < 3; ++q) {
         info->a[q] = p->a[q];
         info->b[q] = p->b[q];
@@ -727,6 +728,13 @@ psn_status psn_plan_query(const psn_plan* p, psn_plan_info* info) {
     info->built = p->built ? 1 : 0;
     info->device_bytes = p->device_bytes;
     info->algorithmic_bytes = algorithmic_bytes(p);
+    return PSN_OK;
+}
+
+psn_status psn_plan_set_correction(psn_plan* p, int mode) {
+    if (!p || (mode != PSN_CORRECTION_FOLDED && mode != PSN_CORRECTION_FOURIER)) return PSN_EINVAL;
+    if (p->built) return PSN_ESTATE;
+    p->correction = mode;
     return PSN_OK;
 }
 

@@ -177,3 +177,15 @@ def test_noalloc_batch_host_checks():
     assert lib.psn_solve_batched_noalloc(0, None, None, None, None) == 0
     assert lib.psn_solve_batched_noalloc(-1, None, None, None, None) == -1
     assert lib.psn_solve_batched_noalloc(1, None, None, None, None) == -1
+
+
+def test_correction_option_host_checks():
+    p = psn.Plan(16, 1.0, 1e-12, "f64")
+    assert p.info()["correction"] == psn.CORRECTION_FOLDED
+    lib = psn._lib
+    assert lib.psn_plan_set_correction(p.handle, 7) == -1
+    assert lib.psn_plan_set_correction(None, 0) == -1
+    assert lib.psn_plan_set_correction(p.handle, psn.CORRECTION_FOURIER) == 0
+    assert p.info()["correction"] == psn.CORRECTION_FOURIER
+    q = psn.Plan(16, 1.0, 1e-12, "f32", correction="fourier")
+    assert q.info()["correction"] == psn.CORRECTION_FOURIER
