@@ -299,15 +299,26 @@ constexpr RadixPlan make_plan(int N, int E) {
     return p;
 }
 
-// Elements per thread for a length-N line: all of N's odd factors times up to
-// 16 (N a power of two; 8 for 8-byte reals) or 4 (N with a factor 3 or 5) of
-// its powers of two.
+// Elements per thread for a length-N line: N's odd factors, at most 15 of
+// them (an odd part above 15, such as 81, keeps its largest divisor up to 9:
+// radix-3 stages then fill the rest), times up to 16 (N a power of two; 8
+// for 8-byte reals) or 4 (N with a factor 3 or 5) of its powers of two.
 constexpr int elems_per_thread(int N, int real_bytes) {
     int odd = N;
     while (odd % 2 == 0) odd /= 2;
     int p2 = N / odd;
     int cap = odd == 1 ? (real_bytes == 8 ? 8 : 16) : 4;
-    return odd * (p2 < cap ? p2 : cap);
+    int oe = odd;
+    if (oe > 15) {
+        oe = 1;
+        for (int d = 9; d >= 1; --d)
+            if (odd % d == 0) {
+                oe = d;
+                break;
+            }
+        cap = 2;
+    }
+    return oe * (p2 < cap ? p2 : cap);
 }
 
 // ----------------------------------------------------------------- twiddle sources

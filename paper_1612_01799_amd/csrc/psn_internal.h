@@ -10,7 +10,7 @@
 
 // Grid sizes compiled into the library: even n with 2n = 2^a 3^b 5^c.
 #define PSN_FOR_EACH_SIZE(X) \
-    X(8) X(12) X(16) X(24) X(32) X(48) X(64) X(96) X(128) X(160) X(192) X(256) X(320) X(384) X(512)
+    X(8) X(12) X(16) X(24) X(32) X(48) X(64) X(96) X(128) X(160) X(162) X(192) X(256) X(320) X(384) X(512)
 
 struct psn_plan {
     // geometry (section 4 grid; padded period 2nh; truncation T = nh), per axis

@@ -77,6 +77,11 @@ constexpr int pick_lines(int N, int T, int cxbytes) {
     int l = 256 / T;
     if (l < 1) l = 1;
     while (l > 1 && (N % l != 0 || (l * rows_padded(N) + ((2 * N + 15) & ~15)) * cxbytes > kMaxLds)) l /= 2;
+    if (l * T < 64) {
+        // halving left less than a wave (odd team sizes): any divisor of N that fits
+        for (int d = 256 / T; d > l; --d)
+            if (N % d == 0 && (d * rows_padded(N) + ((2 * N + 15) & ~15)) * cxbytes <= kMaxLds) return d;
+    }
     return l;
 }
 
@@ -1195,9 +1200,11 @@ struct Sched {
     // longer radix plan).
     static constexpr int odd = N / (N & -N);
     static constexpr int eh = odd * 2;
+    // (the one-chain exchange stages the W2 runs in two rounds of n slots,
+    // which needs the k1 block to divide n)
     static constexpr TileV v24[3] = {
         d24, pick_tile(N, odd > 1 ? TileV{C::BS, N / eh} : TileV{C::BS, N / e16}, d24, C::CX),
-        pick_tile(N, {C::BS, C::T24, 1, true}, d24, C::CX)};
+        N % psn_host::w2_k1_block(N) == 0 ? pick_tile(N, {C::BS, C::T24, 1, true}, d24, C::CX) : d24};
     // P3: one row per workgroup; the row pair k1, M-k1 per workgroup (sizes with
     // an odd factor: with the chains exchanged one at a time); or one row with
     // the chains exchanged one at a time

@@ -38,7 +38,7 @@ def test_library_exports_every_declared_symbol():
 
 
 @pytest.mark.parametrize("n,ok", [(8, True), (12, True), (16, True), (24, True), (48, True), (96, True),
-                                  (160, True), (512, True), (7, False), (14, False), (2, False), (0, False),
+                                  (160, True), (162, True), (512, True), (7, False), (14, False), (2, False), (0, False),
                                   (-8, False), (42, False), (1024 * 8, False)])
 def test_size_rules(n, ok):
     assert psn.size_supported(n) == ok

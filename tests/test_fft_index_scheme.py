@@ -30,7 +30,11 @@ def elems_per_thread(n, real_bytes):
     while odd % 2 == 0:
         odd //= 2
     cap = (8 if real_bytes == 8 else 16) if odd == 1 else 4
-    return odd * min(n // odd, cap)
+    oe = odd
+    if oe > 15:
+        oe = max(d for d in range(1, 10) if odd % d == 0)
+        cap = 2
+    return oe * min(n // odd, cap)
 
 
 def make_plan(n, e):
@@ -148,7 +152,8 @@ def test_forward_output_order_is_reverse_plan_input_order():
 
 @pytest.mark.parametrize("n,e,plan", [(160, 20, [20, 4, 2]), (96, 12, [12, 4, 2]), (320, 20, [20, 4, 4]),
                                       (384, 12, [12, 4, 4, 2]), (12, 12, [12]), (160, 10, [10, 2, 2, 2, 2]),
-                                      (512, 8, [8, 8, 8]), (512, 16, [16, 16, 2]), (256, 16, [16, 16])])
+                                      (512, 8, [8, 8, 8]), (512, 16, [16, 16, 2]), (256, 16, [16, 16]),
+                                      (162, 18, [6, 3, 3, 3])])
 def test_plans_merge_odd_factors(n, e, plan):
     assert make_plan(n, e) == plan
 

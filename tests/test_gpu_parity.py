@@ -16,7 +16,7 @@ from gpu_common import TOL, gpu_solve, max_rel, oracle_octant, oracle_symbol, to
 pytestmark = pytest.mark.gpu
 psn = pytest.importorskip("paper_1612_01799_amd")
 
-SIZES = [8, 12, 16, 24, 32, 48, 64, 96, 128, 160, 192, 320, 384]
+SIZES = [8, 12, 16, 24, 32, 48, 64, 96, 128, 160, 162, 192, 320, 384]
 
 
 def _mix(n, L, seed):
@@ -108,6 +108,21 @@ def test_paper_tables_on_gpu_fp64(entry):
     E = O.error_E(u, ustar)
     digits = 4 if entry in PC.load()["digits"] else 3
     assert abs(E - entry["E"]) <= 0.5 * 10 ** (math.floor(math.log10(entry["E"])) - (digits - 1)) * 1.0001
+
+
+@pytest.mark.parametrize("entry", PC.load()["bounds"], ids=[PC.name(e) for e in PC.load()["bounds"]])
+def test_paper_converged_rows_on_gpu_fp64(entry):
+    """Converged rows (Table 1 at 64^3, Table 6 up to 162^3 on its rectangular
+    box): the FP64 GPU path stays within the printed bound and equals the
+    oracle's result."""
+    torch = torch_cuda()
+    box, rho, ustar = PC.case(entry)
+    eps = entry.get("eps", 1e-12)
+    plan = psn.Plan(box.n[0], box=(box.a, box.b), tol=eps, dtype="f64").build()
+    u = gpu_solve(psn, torch, box.n[0], None, "f64", rho, plan=plan)
+    assert O.error_E(u, ustar) <= entry["max"]
+    ref = O.solve(rho, O.half_spectrum(O.kernel_spectrum(box, eps)))
+    assert max_rel(u, ref) <= TOL["f64"]
 
 
 def test_single_gaussian_closed_form_fp64():
@@ -353,7 +368,7 @@ def test_batched_after_plan_destroyed():
         plan.close()
 
 
-@pytest.mark.parametrize("n", [24, 48, 96, 128, 160, 256])
+@pytest.mark.parametrize("n", [24, 48, 96, 128, 160, 162, 256])
 @pytest.mark.parametrize("dtype", ["f32", "f64", "split"])
 def test_every_schedule_candidate(n, dtype):
     """All compiled tile candidates of the strided passes give the oracle's result."""
