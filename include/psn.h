@@ -114,7 +114,7 @@ psn_status psn_plan_create_box(int n, const double *a, const double *b, double t
  * of section 3): FP64 mode integrals, correction constants C0 and C2 and the
  * octant assembly, then conversion to the plan's storage type; also allocates
  * the solve workspace.  Then picks the tile schedule of the strided passes:
- * each has three compiled candidates, timed once per (n, precision) in the
+ * each has four compiled candidates, timed once per (n, precision) in the
  * process on this plan's workspace (set PSN_TUNE=0 to keep the defaults).
  * With PSN_TUNE_CACHE naming a file, a schedule recorded there for the same
  * (n, precision) is taken without timing, and a newly timed one is appended,
@@ -140,9 +140,13 @@ psn_status psn_solve(psn_plan *p, const void *rho, void *u, void *stream);
  * workspace arena (grown on demand, which synchronises the device; held until
  * the process ends), entries of one (n, precision, schedule) share each
  * kernel launch, and the launch sequence is captured once per argument list
- * and schedule set into a HIP graph and replayed.  The arena is shared by all
- * batched calls on a device, so such calls must not overlap across streams.
- * count == 0 does nothing.
+ * and schedule set into a HIP graph and replayed.  Before the first capture
+ * of a group of two or more entries whose plans were autotuned, the schedule
+ * candidates are timed once on that group's own arena entries (several
+ * entries per launch can favour another candidate than one solve); with
+ * PSN_TUNE=0 or PSN_TUNE_CACHE set the plans' schedules are kept.  The arena
+ * is shared by all batched calls on a device, so such calls must not overlap
+ * across streams.  count == 0 does nothing.
  * Errors: as psn_solve, for the first bad entry; PSN_ENOMEM if the arena
  * cannot grow. */
 psn_status psn_solve_batched(int count, psn_plan *const *plans,
@@ -156,7 +160,8 @@ psn_status psn_solve_batched(int count, psn_plan *const *plans,
  * ends (e.g. two n = 160 FP32 entries or ten n = 96 ones fit; one entry needs
  * about 24 n^3 bytes in FP32, 48 n^3 in F64 and SPLIT).  No graph is captured:
  * the launches are enqueued on `stream` directly, entries of one
- * (n, precision, schedule) sharing each launch.  plans, rho, u as for
+ * (n, precision, schedule) sharing each launch, under the schedule that
+ * psn_solve_batched timed for such a group if it did (else the plans').  plans, rho, u as for
  * psn_solve_batched; the plans must have been built (which also looks the
  * array up on their device).  Every call on a device uses the same array, so
  * calls that overlap on one device (any streams, any plans) race; order them
@@ -174,8 +179,8 @@ psn_status psn_solve_batched_noalloc(int count, psn_plan *const *plans,
  * Errors: as psn_solve. */
 psn_status psn_solve_timed(psn_plan *p, const void *rho, void *u, void *stream, double *pass_ms);
 
-/* Override the tile schedule: candidate p24 (0..2) for the axis-1 passes and
- * p3 (0..2) for the axis-0 pass.  Every candidate computes the same
+/* Override the tile schedule: candidate p24 (0..3) for the axis-1 passes and
+ * p3 (0..3) for the axis-0 pass.  Every candidate computes the same
  * transform; results agree within rounding but not bitwise, since a
  * candidate may run another radix plan or another order of operations.  For
  * one candidate the result is bitwise reproducible.  Errors: PSN_EINVAL. */

@@ -85,17 +85,26 @@ struct Slot {
 // Enqueue the passes for `count` slots that share n and precision (one launch
 // per pass per 32 slots).  With `ev` non-null, ev[0] is recorded before the
 // first pass and ev[i] after pass i (i = 1..5).
-hipError_t launch_group(const Slot* slots, int count, hipStream_t stream, hipEvent_t* ev = nullptr);
-hipError_t launch_group_f64(const Slot* slots, int count, hipStream_t stream, hipEvent_t* ev);
-hipError_t launch_group_f32(const Slot* slots, int count, hipStream_t stream, hipEvent_t* ev);
-hipError_t launch_group_split(const Slot* slots, int count, hipStream_t stream, hipEvent_t* ev);
+// v24/v3 >= 0 override the plans' schedule for this group.
+hipError_t launch_group(const Slot* slots, int count, hipStream_t stream, hipEvent_t* ev = nullptr, int v24 = -1,
+                        int v3 = -1);
+hipError_t launch_group_f64(const Slot* slots, int count, hipStream_t stream, hipEvent_t* ev, int v24, int v3);
+hipError_t launch_group_f32(const Slot* slots, int count, hipStream_t stream, hipEvent_t* ev, int v24, int v3);
+hipError_t launch_group_split(const Slot* slots, int count, hipStream_t stream, hipEvent_t* ev, int v24, int v3);
+
+// Time the schedule candidates on `count` slots sharing n and precision (the
+// first kMaxBatch in one launch; synchronises `stream`); return the fastest.
+hipError_t tune_slots(const Slot* slots, int count, hipStream_t stream, int* best24, int* best3);
+hipError_t tune_slots_f64(const Slot* slots, int count, hipStream_t stream, int* best24, int* best3);
+hipError_t tune_slots_f32(const Slot* slots, int count, hipStream_t stream, int* best24, int* best3);
+hipError_t tune_slots_split(const Slot* slots, int count, hipStream_t stream, int* best24, int* best3);
 
 // Time the compiled tile candidates of the strided passes on the plan's own
 // workspace (synchronises `stream`) and return the fastest.
 hipError_t tune_f64(const psn_plan* p, hipStream_t stream, int* best24, int* best3);
 hipError_t tune_f32(const psn_plan* p, hipStream_t stream, int* best24, int* best3);
 hipError_t tune_split(const psn_plan* p, hipStream_t stream, int* best24, int* best3);
-constexpr int kScheduleCandidates = 3;
+constexpr int kScheduleCandidates = 4;
 
 // Kernel spectrum build on the device (FP64), written into p->K / p->Kb in
 // the plan's storage type, plus C0/C2 into the two doubles at d_c.

@@ -1202,16 +1202,25 @@ struct Sched {
     static constexpr int eh = odd * 2;
     // (the one-chain exchange stages the W2 runs in two rounds of n slots,
     // which needs the k1 block to divide n)
-    static constexpr TileV v24[3] = {
+    // The fourth candidate: sizes with an odd factor halve the elements per
+    // thread and exchange one chain at a time; powers of two take 4 elements
+    // per thread (twice the threads, one more exchange).
+    static constexpr bool seq_ok = N % psn_host::w2_k1_block(N) == 0;
+    static constexpr TileV v24[psn_host::kScheduleCandidates] = {
         d24, pick_tile(N, odd > 1 ? TileV{C::BS, N / eh} : TileV{C::BS, N / e16}, d24, C::CX),
-        N % psn_host::w2_k1_block(N) == 0 ? pick_tile(N, {C::BS, C::T24, 1, true}, d24, C::CX) : d24};
+        seq_ok ? pick_tile(N, {C::BS, C::T24, 1, true}, d24, C::CX) : d24,
+        odd > 1 ? (seq_ok ? pick_tile(N, TileV{C::BS, N / eh, 1, true}, d24, C::CX) : d24)
+                : pick_tile(N, TileV{C::BS, N / 4}, d24, C::CX)};
     // P3: one row per workgroup; the row pair k1, M-k1 per workgroup (sizes with
-    // an odd factor: with the chains exchanged one at a time); or one row with
-    // the chains exchanged one at a time
-    static constexpr TileV v3[3] = {
+    // an odd factor: with the chains exchanged one at a time); one row with
+    // the chains exchanged one at a time; and (odd factor) half the elements
+    // per thread, or (powers of two) 4 elements per thread with the one-chain
+    // exchange
+    static constexpr TileV v3[psn_host::kScheduleCandidates] = {
         d3,
         pick_tile3(N, odd > 1 ? TileV{C::BP3, C::T3, 2, true} : TileV{C::BP3, C::T3, 2}, d3, C::CX, C::BS),
-        pick_tile3(N, {C::BP3, C::T3, 1, true}, d3, C::CX, C::BS)};
+        pick_tile3(N, {C::BP3, C::T3, 1, true}, d3, C::CX, C::BS),
+        pick_tile3(N, odd > 1 ? TileV{C::BP3, N / eh} : TileV{C::BP3, N / 4, 1, true}, d3, C::CX, C::BS)};
     static_assert(tile_ok(N, d24, C::CX) && tile_ok(N, d3, C::CX), "default tiles must fit");
 };
 
@@ -1242,10 +1251,14 @@ struct SchedP {
     // eight points per chain and thread, two chains per exchange round (all
     // four at once halves the workgroups per CU and measured 45 % slower at
     // n = 512); the row pair k1, M-k1 per workgroup; four points per chain
-    // (twice the threads, one more exchange)
+    // (twice the threads, one more exchange); sixteen points per chain (one
+    // exchange fewer, half the threads)
+    static constexpr int e16 = H >= 16 ? 16 : H;
     static constexpr TileP d3{C::BP3, H / e8, 1, 2};
-    static constexpr TileP v3[3] = {d3, pick_tilep(N, TileP{C::BP3, H / e8, 2, 2}, d3, C::CX, C::BS),
-                                    pick_tilep(N, TileP{C::BP3, H / e4, 1, 2}, d3, C::CX, C::BS)};
+    static constexpr TileP v3[psn_host::kScheduleCandidates] = {
+        d3, pick_tilep(N, TileP{C::BP3, H / e8, 2, 2}, d3, C::CX, C::BS),
+        pick_tilep(N, TileP{C::BP3, H / e4, 1, 2}, d3, C::CX, C::BS),
+        pick_tilep(N, TileP{C::BP3, H / e16, 1, 2}, d3, C::CX, C::BS)};
 };
 
 // LDS of the strided passes: the exchange area plus the stage twiddle rows
@@ -1340,12 +1353,14 @@ hipError_t launch_p24(const Batch<DT>& bt, hipStream_t s, int v, bool forward) {
         switch (v) {
             case 1: return forward ? launch_p2p<N, DT, 1>(bt, s) : launch_p4p<N, DT, 1>(bt, s);
             case 2: return forward ? launch_p2p<N, DT, 2>(bt, s) : launch_p4p<N, DT, 2>(bt, s);
+            case 3: return forward ? launch_p2p<N, DT, 3>(bt, s) : launch_p4p<N, DT, 3>(bt, s);
             default: return forward ? launch_p2p<N, DT, 0>(bt, s) : launch_p4p<N, DT, 0>(bt, s);
         }
     } else {
         switch (v) {
             case 1: return forward ? launch_p2<N, DT, 1>(bt, s) : launch_p4<N, DT, 1>(bt, s);
             case 2: return forward ? launch_p2<N, DT, 2>(bt, s) : launch_p4<N, DT, 2>(bt, s);
+            case 3: return forward ? launch_p2<N, DT, 3>(bt, s) : launch_p4<N, DT, 3>(bt, s);
             default: return forward ? launch_p2<N, DT, 0>(bt, s) : launch_p4<N, DT, 0>(bt, s);
         }
     }
@@ -1357,12 +1372,14 @@ hipError_t launch_p3v(const Batch<DT>& bt, hipStream_t s, int v) {
         switch (v) {
             case 1: return launch_p3p<N, DT, 1>(bt, s);
             case 2: return launch_p3p<N, DT, 2>(bt, s);
+            case 3: return launch_p3p<N, DT, 3>(bt, s);
             default: return launch_p3p<N, DT, 0>(bt, s);
         }
     } else {
         switch (v) {
             case 1: return launch_p3<N, DT, 1>(bt, s);
             case 2: return launch_p3<N, DT, 2>(bt, s);
+            case 3: return launch_p3<N, DT, 3>(bt, s);
             default: return launch_p3<N, DT, 0>(bt, s);
         }
     }
@@ -1420,9 +1437,11 @@ hipError_t tune_n(const Batch<DT>& bt, hipStream_t s, int* best24, int* best3) {
     };
     // Candidates are timed in interleaved rounds (so clock changes hit all of
     // them alike); each keeps its best time; round 0 only warms up.
-    float t24[3] = {1e30f, 1e30f, 1e30f}, t3[3] = {1e30f, 1e30f, 1e30f};
+    constexpr int NC = psn_host::kScheduleCandidates;
+    float t24[NC], t3[NC];
+    for (int v = 0; v < NC; ++v) t24[v] = t3[v] = 1e30f;
     for (int round = 0; round < 7 && e == hipSuccess; ++round) {
-        for (int v = 0; v < 3 && e == hipSuccess; ++v) {
+        for (int v = 0; v < NC && e == hipSuccess; ++v) {
             float x = 0.f, y = 0.f;
             e = timed([&] {
                     hipError_t r = launch_p24<N, DT>(bt, s, v, true);
@@ -1440,7 +1459,7 @@ hipError_t tune_n(const Batch<DT>& bt, hipStream_t s, int* best24, int* best3) {
     if (e != hipSuccess) return e;
     *best24 = 0;
     *best3 = 0;
-    for (int v = 1; v < 3; ++v) {
+    for (int v = 1; v < NC; ++v) {
         if (t24[v] < 0.97f * t24[*best24]) *best24 = v;
         if (t3[v] < 0.97f * t3[*best3]) *best3 = v;
     }
@@ -1484,10 +1503,12 @@ CorrProb<DT> corr_of(const psn_host::Slot& sl) {
     return c;
 }
 
-// Slots [0, count) share n, precision and schedule (the caller groups them so).
+// Slots [0, count) share n, precision and schedule (the caller groups them
+// so); v24/v3 >= 0 override the plans' schedule.
 template <int DT>
-hipError_t solve_group(const psn_host::Slot* slots, int count, hipStream_t s, hipEvent_t* ev) {
-    const int v24 = slots[0].plan->sched24, v3 = slots[0].plan->sched3;
+hipError_t solve_group(const psn_host::Slot* slots, int count, hipStream_t s, hipEvent_t* ev, int v24o = -1,
+                       int v3o = -1) {
+    const int v24 = v24o >= 0 ? v24o : slots[0].plan->sched24, v3 = v3o >= 0 ? v3o : slots[0].plan->sched3;
     for (int base = 0; base < count; base += kMaxBatch) {
         Batch<DT> bt{};
         CorrBatch<DT> cb{};
@@ -1511,6 +1532,23 @@ hipError_t solve_group(const psn_host::Slot* slots, int count, hipStream_t s, hi
     return hipSuccess;
 }
 
+// Time the candidates on a batch group's own entries (their workspaces in
+// the batch arena; contents are irrelevant to the timing): the first
+// kMaxBatch of them in one launch, as the batch runs them.
+template <int DT>
+hipError_t tune_slots(const psn_host::Slot* slots, int count, hipStream_t s, int* best24, int* best3) {
+    Batch<DT> bt{};
+    bt.count = count < kMaxBatch ? count : kMaxBatch;
+    for (int i = 0; i < bt.count; ++i) bt.p[i] = prob_of<DT>(slots[i]);
+    switch (slots[0].plan->n) {
+#define PSN_CASE(NN) \
+    case NN: return tune_n<NN, DT>(bt, s, best24, best3);
+        PSN_FOR_EACH_SIZE(PSN_CASE)
+#undef PSN_CASE
+        default: return hipErrorInvalidValue;
+    }
+}
+
 template <int DT>
 hipError_t tune_plan(const psn_plan* p, hipStream_t s, int* best24, int* best3) {
     Batch<DT> bt{};
@@ -1530,8 +1568,12 @@ hipError_t tune_plan(const psn_plan* p, hipStream_t s, int* best24, int* best3) 
 // Defines the per-precision entry points of one compilation unit.
 #define PSN_DEFINE_PRECISION(DTV, SUFFIX)                                                                       \
     namespace psn_host {                                                                                        \
-    hipError_t launch_group_##SUFFIX(const Slot* slots, int count, hipStream_t stream, hipEvent_t* ev) {       \
-        return psn::solve_group<DTV>(slots, count, stream, ev);                                                 \
+    hipError_t launch_group_##SUFFIX(const Slot* slots, int count, hipStream_t stream, hipEvent_t* ev, int v24, \
+                                     int v3) {                                                                  \
+        return psn::solve_group<DTV>(slots, count, stream, ev, v24, v3);                                        \
+    }                                                                                                           \
+    hipError_t tune_slots_##SUFFIX(const Slot* slots, int count, hipStream_t stream, int* best24, int* best3) { \
+        return psn::tune_slots<DTV>(slots, count, stream, best24, best3);                                       \
     }                                                                                                           \
     hipError_t tune_##SUFFIX(const psn_plan* p, hipStream_t stream, int* best24, int* best3) {                \
         return psn::tune_plan<DTV>(p, stream, best24, best3);                                                   \

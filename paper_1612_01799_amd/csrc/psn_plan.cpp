@@ -268,6 +268,9 @@ struct BatchCache {
     std::vector<hipEvent_t> join;
     hipEvent_t fork = nullptr;
     std::map<std::vector<const void*>, hipGraphExec_t> graphs;
+    // schedules timed on batch groups: (n, precision, plan schedule, entries
+    // per launch) -> (axis-1 candidate, axis-0 candidate)
+    std::map<std::array<int, 5>, std::pair<int, int>> group_sched;
     // A graph may still run on the stream it was launched on (any stream of
     // the caller's), so the device is drained before any is destroyed.
     void clear_graphs() {
@@ -314,12 +317,21 @@ bool scratch_ptr(int dev, void** out) {
 
 namespace psn_host {
 
-hipError_t launch_group(const Slot* slots, int count, hipStream_t stream, hipEvent_t* ev) {
+hipError_t launch_group(const Slot* slots, int count, hipStream_t stream, hipEvent_t* ev, int v24, int v3) {
     if (count <= 0) return hipSuccess;
     switch (slots[0].plan->dtype) {
-        case PSN_F64: return launch_group_f64(slots, count, stream, ev);
-        case PSN_F32: return launch_group_f32(slots, count, stream, ev);
-        case PSN_SPLIT: return launch_group_split(slots, count, stream, ev);
+        case PSN_F64: return launch_group_f64(slots, count, stream, ev, v24, v3);
+        case PSN_F32: return launch_group_f32(slots, count, stream, ev, v24, v3);
+        case PSN_SPLIT: return launch_group_split(slots, count, stream, ev, v24, v3);
+    }
+    return hipErrorInvalidValue;
+}
+
+hipError_t tune_slots(const Slot* slots, int count, hipStream_t stream, int* best24, int* best3) {
+    switch (slots[0].plan->dtype) {
+        case PSN_F64: return tune_slots_f64(slots, count, stream, best24, best3);
+        case PSN_F32: return tune_slots_f32(slots, count, stream, best24, best3);
+        case PSN_SPLIT: return tune_slots_split(slots, count, stream, best24, best3);
     }
     return hipErrorInvalidValue;
 }
@@ -588,6 +600,34 @@ psn_status psn_solve_batched(int count, psn_plan* const* plans, const void* cons
             chains[c].push_back(o.second);
             load[c] += o.first;
         }
+        // Several entries sharing a launch run best under the schedule timed on
+        // such a launch, which can differ from the single-solve choice: a
+        // group of autotuned plans is timed once on its own arena entries (on
+        // the caller's stream, after the work already queued there).  Off
+        // with PSN_TUNE=0 or a PSN_TUNE_CACHE file (whose choices are kept).
+        std::map<const std::vector<psn_host::Slot>*, std::pair<int, int>> gsched;
+        {
+            const char* env = std::getenv("PSN_TUNE");
+            const char* cache = std::getenv("PSN_TUNE_CACHE");
+            const bool tune = !(env && env[0] == '0') && !(cache && cache[0]);
+            for (auto& g : groups) {
+                const psn_plan* p0 = g.second.front().plan;
+                bool all_tuned = g.second.size() >= 2;
+                for (const auto& sl : g.second) all_tuned = all_tuned && sl.plan->tuned;
+                if (!tune || !all_tuned) continue;
+                const int per_launch = int(std::min<size_t>(g.second.size(), size_t(psn::kMaxBatchHost)));
+                const std::array<int, 5> gk{p0->n, int(p0->dtype), p0->sched24, p0->sched3, per_launch};
+                auto gi = bc.group_sched.find(gk);
+                if (gi == bc.group_sched.end()) {
+                    int b24 = 0, b3 = 0;
+                    if (!hip_ok(psn_host::tune_slots(g.second.data(), int(g.second.size()), s, &b24, &b3),
+                                "batch schedule tuning"))
+                        return PSN_EDEVICE;
+                    gi = bc.group_sched.emplace(gk, std::make_pair(b24, b3)).first;
+                }
+                gsched[&g.second] = gi->second;
+            }
+        }
         if (!bc.capture && !hip_ok(hipStreamCreateWithFlags(&bc.capture, hipStreamNonBlocking), "hipStreamCreate"))
             return PSN_EDEVICE;
         if (!bc.fork && !hip_ok(hipEventCreateWithFlags(&bc.fork, hipEventDisableTiming), "hipEventCreate"))
@@ -614,7 +654,10 @@ psn_status psn_solve_batched(int count, psn_plan* const* plans, const void* cons
             hipStream_t st = ci == 0 ? bc.capture : bc.branch[ci - 1];
             for (const auto* g : chains[ci]) {
                 if (le != hipSuccess) break;
-                le = psn_host::launch_group(g->data(), int(g->size()), st);
+                const auto gs = gsched.find(g);
+                le = gs == gsched.end() ? psn_host::launch_group(g->data(), int(g->size()), st)
+                                        : psn_host::launch_group(g->data(), int(g->size()), st, nullptr,
+                                                                 gs->second.first, gs->second.second);
             }
         }
         for (size_t ci = 1; ci < nchain && le == hipSuccess; ++ci) {
@@ -677,6 +720,29 @@ psn_status psn_solve_batched_noalloc(int count, psn_plan* const* plans, const vo
     for (int i = 0; i < count; ++i) {
         if (done[i]) continue;
         const psn_plan* p0 = plans[i];
+        // the schedule a batched call timed for such a group, if any (lookup only)
+        int gsize = 0;
+        for (int j = i; j < count; ++j) {
+            const psn_plan* pj = plans[j];
+            gsize += (!done[j] && pj->n == p0->n && pj->dtype == p0->dtype && pj->sched24 == p0->sched24 &&
+                      pj->sched3 == p0->sched3)
+                         ? 1
+                         : 0;
+        }
+        int v24 = -1, v3 = -1;
+        {
+            std::lock_guard<std::mutex> lock(g_batch_mutex);
+            auto bi = g_batch.find(dev);
+            if (bi != g_batch.end()) {
+                const std::array<int, 5> gk{p0->n, int(p0->dtype), p0->sched24, p0->sched3,
+                                            std::min(gsize, psn::kMaxBatchHost)};
+                auto gi = bi->second.group_sched.find(gk);
+                if (gi != bi->second.group_sched.end()) {
+                    v24 = gi->second.first;
+                    v3 = gi->second.second;
+                }
+            }
+        }
         size_t off = 0;
         int g = 0;
         for (int j = 0; j < count; ++j) {
@@ -686,13 +752,15 @@ psn_status psn_solve_batched_noalloc(int count, psn_plan* const* plans, const vo
                 group[g++] = arena_slot(pj, rho[j], u[j], static_cast<char*>(base) + off);
                 done[j] = true;
                 if (g == psn::kMaxBatchHost) {
-                    if (!hip_ok(psn_host::launch_group(group, g, s), "batch launch")) return PSN_EDEVICE;
+                    if (!hip_ok(psn_host::launch_group(group, g, s, nullptr, v24, v3), "batch launch"))
+                        return PSN_EDEVICE;
                     g = 0;
                 }
             }
             off += slot_bytes(pj);
         }
-        if (g > 0 && !hip_ok(psn_host::launch_group(group, g, s), "batch launch")) return PSN_EDEVICE;
+        if (g > 0 && !hip_ok(psn_host::launch_group(group, g, s, nullptr, v24, v3), "batch launch"))
+            return PSN_EDEVICE;
     }
     return PSN_OK;
 }

@@ -378,8 +378,8 @@ def test_every_schedule_candidate(n, dtype):
     ref = O.solve(rho, oracle_symbol(n, L))
     plan = psn.Plan(n, L, 1e-12, dtype).build()
     info = plan.info()
-    assert info["tuned"] == 1 and all(0 <= v < 3 for v in info["schedule"])
-    for s in [(0, 0), (1, 1), (2, 2), (1, 2), (2, 0)]:
+    assert info["tuned"] == 1 and all(0 <= v < 4 for v in info["schedule"])
+    for s in [(0, 0), (1, 1), (2, 2), (3, 3), (1, 2), (2, 0), (3, 0), (0, 3)]:
         plan.set_schedule(*s)
         u = gpu_solve(psn, torch, n, L, dtype, rho, plan=plan)
         assert max_rel(u, ref) <= TOL[dtype], s
@@ -393,7 +393,7 @@ def test_every_schedule_candidate_n512():
         _cache512["rho"] = rho
         _cache512["ref"] = O.solve(rho, O.half_spectrum(_ks512()))
     plan = psn.Plan(512, 12.0, 1e-12, "f32").build()
-    for s in [(0, 0), (1, 1), (2, 2)]:
+    for s in [(0, 0), (1, 1), (2, 2), (3, 3)]:
         plan.set_schedule(*s)
         u = gpu_solve(psn, torch, 512, 12.0, "f32", _cache512["rho"], plan=plan)
         assert max_rel(u, _cache512["ref"]) <= TOL["f32"], s
@@ -410,8 +410,8 @@ def test_bitwise_determinism_every_schedule(n, dtype):
     rho_np = _mix(n, L, 500 + n)
     plan = psn.Plan(n, L, 1e-12, dtype).build()
     rho = torch.from_numpy(rho_np).to("cuda", plan.io_dtype())
-    for v24 in range(3):
-        for v3 in range(3):
+    for v24 in range(4):
+        for v3 in range(4):
             plan.set_schedule(v24, v3)
             a = plan.solve(rho)
             b = plan.solve(rho)
