@@ -91,6 +91,7 @@ typedef struct {
     int tuned;          /* 1 if the schedule came from the autotuner (or its cache file) */
     int device;         /* HIP device the kernel spectrum was built on; -1 before the build */
     int correction;     /* psn_correction */
+    int n3[3];          /* points per axis (all n for psn_plan_create and _box) */
 } psn_plan_info;
 
 /* Create a plan for an n^3 grid on [-L, L]^3 (the solver construction of the
@@ -109,6 +110,19 @@ psn_status psn_plan_create(int n, double L, double tol, psn_dtype dtype, psn_pla
  * Errors: PSN_EINVAL, PSN_ESIZE, PSN_EFIT. */
 psn_status psn_plan_create_box(int n, const double *a, const double *b, double tol, psn_dtype dtype,
                                psn_plan **out);
+
+/* As psn_plan_create_box with n[q] points on axis q (arrays of 3: the paper's
+ * general box with N = n0 n1 n2 points, section 2 and section 3): spacing
+ * h_q = (b_q - a_q)/(n_q - 1), per-axis mode tables, delta from
+ * min_q (b_q - a_q)/(50 n_q).  Each n_q must be a supported size.  Equal sizes
+ * give the same plan as psn_plan_create_box.  Otherwise the plan runs the
+ * five steps on plain workspaces (W1 n0 n1 (n2+1), W2 2 n0 n1 (n2+1) complex;
+ * split precision stores them in FP64), has no tile schedules
+ * (psn_plan_set_schedule: PSN_EINVAL), takes only the folded correction, and
+ * psn_kernel_download fills (n0+1)(n1+1)(n2+1) values.
+ * Errors: PSN_EINVAL, PSN_ESIZE, PSN_EFIT. */
+psn_status psn_plan_create_grid(const int *n, const double *a, const double *b, double tol, psn_dtype dtype,
+                                psn_plan **out);
 
 /* Build the kernel spectrum on the current device (the G-tensor precomputation
  * of section 3): FP64 mode integrals, correction constants C0 and C2 and the
@@ -207,9 +221,10 @@ psn_status psn_plan_query(const psn_plan *p, psn_plan_info *info);
  * *terms; copies min(cap, terms) entries.  Errors: PSN_EINVAL. */
 psn_status psn_plan_gs_table(const psn_plan *p, double *tau, double *w, int cap, int *terms);
 
-/* Copy the built kernel spectrum to a host array octant[(n+1)^3], FP64, index
- * [k0][k1][k2] with k_q = 0..n the folded frequency index, in the paper's
- * normalisation (no 1/(2n)^3 factor).  Synchronous.
+/* Copy the built kernel spectrum to a host array octant[(n0+1)(n1+1)(n2+1)]
+ * ((n+1)^3 on a grid of n points per axis), FP64, index [k0][k1][k2] with
+ * k_q = 0..n_q the folded frequency index, in the paper's normalisation (no
+ * 1/(8 n0 n1 n2) factor).  Synchronous.
  * Errors: PSN_EINVAL, PSN_ESTATE, PSN_EDEVICE. */
 psn_status psn_kernel_download(const psn_plan *p, double *octant);
 

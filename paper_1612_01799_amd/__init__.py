@@ -50,6 +50,7 @@ class PlanInfo(ctypes.Structure):
         ("algorithmic_bytes", ctypes.c_double), ("a", ctypes.c_double * 3), ("b", ctypes.c_double * 3),
         ("h3", ctypes.c_double * 3), ("T3", ctypes.c_double * 3), ("schedule", ctypes.c_int * 2),
         ("tuned", ctypes.c_int), ("device", ctypes.c_int), ("correction", ctypes.c_int),
+        ("n3", ctypes.c_int * 3),
     ]
 
 
@@ -70,6 +71,9 @@ def _load():
         "psn_plan_create_box": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(ctypes.c_double),
                                                ctypes.POINTER(ctypes.c_double), ctypes.c_double, ctypes.c_int,
                                                ctypes.POINTER(P)]),
+        "psn_plan_create_grid": (ctypes.c_int, [ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_double),
+                                                ctypes.POINTER(ctypes.c_double), ctypes.c_double, ctypes.c_int,
+                                                ctypes.POINTER(P)]),
         "psn_kernel_build": (ctypes.c_int, [P, P]),
         "psn_solve": (ctypes.c_int, [P, P, P, P]),
         "psn_solve_timed": (ctypes.c_int, [P, P, P, P, ctypes.POINTER(ctypes.c_double)]),
@@ -121,25 +125,33 @@ def _stream_handle(stream):
 class Plan:
     """One grid geometry: n^3 points on [-L, L]^3 (or on the box a..b when
     `box=(a, b)` is given, a and b 3-sequences), Gaussian-sum tolerance tol.
+    `n` may be a 3-sequence of per-axis point counts (psn_plan_create_grid).
     `correction` is "folded" (the near-zone correction's symbol added to the
     kernel spectrum) or "fourier" (added after the convolution, with the
     Laplacian from the density's size-N Fourier series)."""
 
-    def __init__(self, n: int, L: float = None, tol: float = 1e-12, dtype="f32", box=None,
+    def __init__(self, n, L: float = None, tol: float = 1e-12, dtype="f32", box=None,
                  correction="folded"):
         self._h = ctypes.c_void_p()
-        self.n = int(n)
+        n3 = tuple(int(v) for v in n) if isinstance(n, (tuple, list)) else (int(n),) * 3
+        if len(n3) != 3:
+            raise ValueError("n must be an int or a 3-sequence")
+        self.n = n3[0]
+        self.shape = n3
         self.dtype = _DTYPES[dtype]
-        if box is None:
+        if box is None and len(set(n3)) == 1:
             self.L = float(L)
             _check(_lib.psn_plan_create(self.n, self.L, float(tol), self.dtype, ctypes.byref(self._h)),
                    "psn_plan_create")
         else:
+            if box is None:
+                box = ((-float(L),) * 3, (float(L),) * 3)
             a = (ctypes.c_double * 3)(*[float(v) for v in box[0]])
             b = (ctypes.c_double * 3)(*[float(v) for v in box[1]])
             self.L = max(0.5 * (b[q] - a[q]) for q in range(3))
-            _check(_lib.psn_plan_create_box(self.n, a, b, float(tol), self.dtype, ctypes.byref(self._h)),
-                   "psn_plan_create_box")
+            nn = (ctypes.c_int * 3)(*n3)
+            _check(_lib.psn_plan_create_grid(nn, a, b, float(tol), self.dtype, ctypes.byref(self._h)),
+                   "psn_plan_create_grid")
         if _CORRECTIONS[correction] != CORRECTION_FOLDED:
             _check(_lib.psn_plan_set_correction(self._h, _CORRECTIONS[correction]), "psn_plan_set_correction")
 
@@ -163,14 +175,13 @@ class Plan:
         of the plan's shape and I/O dtype on the plan's device: a host pointer
         reaching a kernel is a GPU page fault, a wrong dtype a wrong result."""
         import torch
-        n = self.n
         for name, t in (("rho", rho), ("out", out)):
             if not isinstance(t, torch.Tensor):
                 raise ValueError(f"{what}: {name} must be a torch tensor")
             if not t.is_cuda:
                 raise ValueError(f"{what}: {name} must be a CUDA tensor (got device {t.device})")
-            if tuple(t.shape) != (n, n, n) or t.dtype != self.io_dtype() or not t.is_contiguous():
-                raise ValueError(f"{what}: {name} must be a contiguous ({n},{n},{n}) {self.io_dtype()} tensor, "
+            if tuple(t.shape) != self.shape or t.dtype != self.io_dtype() or not t.is_contiguous():
+                raise ValueError(f"{what}: {name} must be a contiguous {self.shape} {self.io_dtype()} tensor, "
                                  f"got {tuple(t.shape)} {t.dtype} contiguous={t.is_contiguous()}")
         dev = self.device()
         if dev < 0:
@@ -229,7 +240,7 @@ class Plan:
 
     def kernel_octant(self):
         import numpy as np
-        k = np.empty((self.n + 1,) * 3)
+        k = np.empty(tuple(v + 1 for v in self.shape))
         _check(_lib.psn_kernel_download(self._h, k.ctypes.data_as(ctypes.POINTER(ctypes.c_double))),
                "psn_kernel_download")
         return k

@@ -18,7 +18,8 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpsn.so")
 ARCH = "gfx950"
 
-SOURCES = ["psn_passes_f32.hip", "psn_passes_f64.hip", "psn_passes_split.hip", "psn_kbuild.hip", "psn_plan.cpp"]
+SOURCES = ["psn_passes_f32.hip", "psn_passes_f64.hip", "psn_passes_split.hip", "psn_general_f32.hip",
+           "psn_general_f64.hip", "psn_kbuild.hip", "psn_plan.cpp"]
 
 FLAGS = [
     "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
@@ -37,7 +38,7 @@ def _hipcc():
     raise RuntimeError("hipcc not found")
 
 
-def build_library(verbose: bool = False, jobs: int = 5) -> str:
+def build_library(verbose: bool = False, jobs: int = 7) -> str:
     hipcc = _hipcc()
     objdir = os.path.join(HERE, "_build")
     os.makedirs(objdir, exist_ok=True)

@@ -40,6 +40,10 @@ struct psn_plan {
     bool tuned = false;
     // near-zone correction: folded into K, or added by its Fourier series
     int correction = PSN_CORRECTION_FOLDED;
+    // points per axis; `general` when they differ (the five-step path with
+    // plain workspaces and a plain [k0][k1][k2] octant)
+    int ng[3] = {0, 0, 0};
+    bool general = false;
 };
 
 namespace psn {
@@ -91,6 +95,11 @@ hipError_t launch_group(const Slot* slots, int count, hipStream_t stream, hipEve
 hipError_t launch_group_f64(const Slot* slots, int count, hipStream_t stream, hipEvent_t* ev, int v24, int v3);
 hipError_t launch_group_f32(const Slot* slots, int count, hipStream_t stream, hipEvent_t* ev, int v24, int v3);
 hipError_t launch_group_split(const Slot* slots, int count, hipStream_t stream, hipEvent_t* ev, int v24, int v3);
+
+// The five-step solve of a grid with per-axis sizes, one slot (FP32, or
+// FP64 arithmetic and storage for F64 and split-precision plans).
+hipError_t launch_general_f32(const Slot& sl, hipStream_t stream, hipEvent_t* ev);
+hipError_t launch_general_f64(const Slot& sl, hipStream_t stream, hipEvent_t* ev);
 
 // Time the schedule candidates on `count` slots sharing n and precision (the
 // first kMaxBatch in one launch; synchronises `stream`); return the fastest.

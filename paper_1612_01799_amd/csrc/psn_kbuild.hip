@@ -21,6 +21,8 @@
 // three axes share one mode table and K is symmetric in (k0, k1); then only
 // k0 <= k1 is computed, the pair product a_j(k0) a_j(k1) is formed first (so
 // both halves agree bitwise) and each value is written to both places.
+#include <algorithm>
+
 #include "psn_device.h"
 #include "psn_internal.h"
 
@@ -293,6 +295,24 @@ __global__ void __launch_bounds__(256) k_gemm(const double* __restrict__ A0, con
     }
 }
 
+// Octant of a grid with per-axis sizes, plain layout [k0][k1][k2] with
+// k_q = 0..n_q: one thread per k2, sum over the terms.  A_q has rows of n_q + 1.
+template <class Kt>
+__global__ void g_assemble(const double* __restrict__ A0, const double* __restrict__ A1,
+                           const double* __restrict__ A2, const double* __restrict__ w, int terms, int n0, int n1,
+                           int n2, double p0, double p1, double p2, const double* __restrict__ Cc, double fold,
+                           double scale, Kt* __restrict__ K) {
+    const int k2 = blockIdx.x * blockDim.x + threadIdx.x, k1 = blockIdx.y, k0 = blockIdx.z;
+    if (k2 > n2) return;
+    double s = 0.0;
+    for (int j = 0; j < terms; ++j)
+        s = fma(A0[size_t(j) * (n0 + 1) + k0] * A1[size_t(j) * (n1 + 1) + k1], w[j] * A2[size_t(j) * (n2 + 1) + k2],
+                s);
+    const double b0 = 2.0 * kPi * k0 / p0, b1 = 2.0 * kPi * k1 / p1, b2 = 2.0 * kPi * k2 / p2;
+    const double v = s + fold * (Cc[0] - (Cc[1] / 6.0) * (b0 * b0 + b1 * b1 + b2 * b2));
+    K[(size_t(k0) * (n1 + 1) + k1) * (n2 + 1) + k2] = Kt(scale * v);
+}
+
 }  // namespace psn
 
 namespace psn_host {
@@ -305,25 +325,28 @@ size_t kbuild_scratch_doubles(int n, int terms) {
 hipError_t launch_kernel_build(psn_plan* p, const double* d_tau, const double* d_w, int terms, const double* d_glx,
                                const double* d_glw, double* d_A, double* d_c, hipStream_t s) {
     const int n = p->n;
-    const size_t np1 = size_t(n) + 1;
+    const int nmax = std::max(p->ng[0], std::max(p->ng[1], p->ng[2]));
+    const size_t np1 = size_t(nmax) + 1;
     const size_t tab = size_t(terms) * np1;
-    double* d_mom = d_A + 3 * tab;                       // 3 x kMoments x (n+1)
+    double* d_mom = d_A + 3 * tab;                           // 3 x kMoments x (nmax+1)
     double* d_kn = d_mom + 3 * size_t(psn::kMoments) * np1;  // (n+1)^2
-    // one mode table per distinct axis length
+    // one mode table per distinct axis (length, period, points); table q has
+    // rows of ng[q] + 1 entries
     const double* A[3];
     for (int q = 0; q < 3; ++q) {
         int same = -1;
         for (int r = 0; r < q; ++r)
-            if (p->T[r] == p->T[q] && p->period[r] == p->period[q]) same = r;
+            if (p->T[r] == p->T[q] && p->period[r] == p->period[q] && p->ng[r] == p->ng[q]) same = r;
         if (same >= 0) {
             A[q] = A[same];
             continue;
         }
+        const int nq = p->ng[q];
         A[q] = d_A + q * tab;
         double* mom = d_mom + q * size_t(psn::kMoments) * np1;
-        hipLaunchKernelGGL(psn::k_moments, dim3(n + 1), dim3(psn::kPanelThreads), 0, s, n, p->T[q], p->period[q],
+        hipLaunchKernelGGL(psn::k_moments, dim3(nq + 1), dim3(psn::kPanelThreads), 0, s, nq, p->T[q], p->period[q],
                            d_glx, d_glw, mom);
-        hipLaunchKernelGGL(psn::k_modes, dim3((n + 1 + 127) / 128, terms), dim3(128), 0, s, d_tau, n, p->T[q],
+        hipLaunchKernelGGL(psn::k_modes, dim3((nq + 1 + 127) / 128, terms), dim3(128), 0, s, d_tau, nq, p->T[q],
                            p->period[q], mom, d_A + q * tab);
         // the terms with 1 <= tau T < 6.1: a contiguous range (tau grows with j)
         int j0 = terms, j1 = 0;
@@ -335,10 +358,22 @@ hipError_t launch_kernel_build(psn_plan* p, const double* d_tau, const double* d
             }
         }
         if (j1 > j0)
-            hipLaunchKernelGGL(psn::k_modes_mid, dim3(n + 1, j1 - j0), dim3(psn::kPanelThreads), 0, s, d_tau, j0, n,
+            hipLaunchKernelGGL(psn::k_modes_mid, dim3(nq + 1, j1 - j0), dim3(psn::kPanelThreads), 0, s, d_tau, j0, nq,
                                p->T[q], p->period[q], d_glx, d_glw, d_A + q * tab);
     }
     hipLaunchKernelGGL(psn::k_correction, dim3(1), dim3(256), 0, s, d_tau, d_w, terms, p->delta, d_c);
+    if (p->general) {
+        const int n0 = p->ng[0], n1 = p->ng[1], n2 = p->ng[2];
+        const double scale = 1.0 / (8.0 * double(n0) * n1 * n2);
+        const dim3 g((n2 + 1 + 127) / 128, n1 + 1, n0 + 1);
+        if (p->dtype == PSN_F32)
+            hipLaunchKernelGGL(psn::g_assemble<float>, g, dim3(128), 0, s, A[0], A[1], A[2], d_w, terms, n0, n1, n2,
+                               p->period[0], p->period[1], p->period[2], d_c, 1.0, scale, static_cast<float*>(p->K));
+        else
+            hipLaunchKernelGGL(psn::g_assemble<double>, g, dim3(128), 0, s, A[0], A[1], A[2], d_w, terms, n0, n1, n2,
+                               p->period[0], p->period[1], p->period[2], d_c, 1.0, scale, static_cast<double*>(p->K));
+        return hipGetLastError();
+    }
     // the correction symbol is folded into K unless the plan adds it by the
     // Fourier series of the density (then fold = 0 leaves the G-tensor alone)
     const double fold = p->correction == PSN_CORRECTION_FOURIER ? 0.0 : 1.0;

@@ -218,14 +218,27 @@ size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
 // its arrays (io: rho and u, s: complex intermediates per real, k: kernel
 // spectrum per real)
 double algorithmic_bytes(const psn_plan* p) {
-    const double n3 = double(p->n) * p->n * p->n, np1 = p->n + 1.0;
     const double bio = p->dtype == PSN_F32 ? 4 : 8;
-    const double bs = p->dtype == PSN_F32 ? 4 : (p->dtype == PSN_F64 ? 8 : 6);
     const double bk = p->dtype == PSN_F32 ? 4 : 8;
+    if (p->general) {
+        // W1 = n0 n1 (n2+1) and W2 = 2 n0 n1 (n2+1) complex (FP64 storage
+        // for the FP64-arithmetic precisions), K = (n0+1)(n1+1)(n2+1) reals
+        const double bs = p->dtype == PSN_F32 ? 4 : 8;
+        const double n0 = p->ng[0], n1 = p->ng[1], n2 = p->ng[2];
+        return 2 * bio * n0 * n1 * n2 + 24 * bs * n0 * n1 * (n2 + 1) + bk * (n0 + 1) * (n1 + 1) * (n2 + 1);
+    }
+    const double n3 = double(p->n) * p->n * p->n, np1 = p->n + 1.0;
+    const double bs = p->dtype == PSN_F32 ? 4 : (p->dtype == PSN_F64 ? 8 : 6);
     return 2 * bio * n3 + 24 * bs * n3 + bk * np1 * np1 * np1;
 }
 
+// complex workspace elements of a grid with per-axis sizes
+size_t general_w1(const psn_plan* p) { return size_t(p->ng[0]) * p->ng[1] * (p->ng[2] + 1); }
+size_t general_w2(const psn_plan* p) { return 2 * general_w1(p); }
+size_t general_cx(const psn_plan* p) { return p->dtype == PSN_F32 ? 8 : 16; }
+
 size_t slot_bytes(const psn_plan* p) {
+    if (p->general) return align256(general_w1(p) * general_cx(p)) + align256(general_w2(p) * general_cx(p));
     const size_t n3 = size_t(p->n) * p->n * p->n;
     const size_t wb = p->dtype == PSN_SPLIT ? 8 : psn_host::elem_bytes(p->dtype);
     const size_t w2 = psn_host::w2_elems(p->n);
@@ -242,6 +255,11 @@ psn_host::Slot arena_slot(const psn_plan* p, const void* rho, void* u, char* bas
     const size_t n3 = size_t(p->n) * p->n * p->n;
     const size_t wb = p->dtype == PSN_SPLIT ? 8 : psn_host::elem_bytes(p->dtype);
     psn_host::Slot sl{p, rho, u, nullptr, nullptr, nullptr, nullptr};
+    if (p->general) {
+        sl.W1 = base;
+        sl.W2 = base + align256(general_w1(p) * general_cx(p));
+        return sl;
+    }
     sl.W1 = base;
     base += align256(n3 * wb);
     sl.W2 = base;
@@ -319,6 +337,15 @@ namespace psn_host {
 
 hipError_t launch_group(const Slot* slots, int count, hipStream_t stream, hipEvent_t* ev, int v24, int v3) {
     if (count <= 0) return hipSuccess;
+    if (slots[0].plan->general) {
+        // grids with per-axis sizes: the five steps, one entry after the other
+        for (int i = 0; i < count; ++i) {
+            const hipError_t e = slots[i].plan->dtype == PSN_F32 ? launch_general_f32(slots[i], stream, ev)
+                                                                 : launch_general_f64(slots[i], stream, ev);
+            if (e != hipSuccess) return e;
+        }
+        return hipSuccess;
+    }
     switch (slots[0].plan->dtype) {
         case PSN_F64: return launch_group_f64(slots, count, stream, ev, v24, v3);
         case PSN_F32: return launch_group_f32(slots, count, stream, ev, v24, v3);
@@ -357,29 +384,33 @@ int psn_size_supported(int n) {
     return (n >= 4 && n % 2 == 0 && five_smooth(2L * n) && psn_host::size_compiled(n)) ? 1 : 0;
 }
 
-psn_status psn_plan_create_box(int n, const double* a, const double* b, double tol, psn_dtype dtype,
-                               psn_plan** out) {
+psn_status psn_plan_create_grid(const int* n3, const double* a, const double* b, double tol, psn_dtype dtype,
+                                psn_plan** out) {
     if (!out) return PSN_EINVAL;
     *out = nullptr;
-    if (!a || !b || !is_real_dtype(dtype) || !(tol >= 1e-15 && tol <= 1e-4)) return PSN_EINVAL;
+    if (!n3 || !a || !b || !is_real_dtype(dtype) || !(tol >= 1e-15 && tol <= 1e-4)) return PSN_EINVAL;
     for (int q = 0; q < 3; ++q)
         if (!std::isfinite(a[q]) || !std::isfinite(b[q]) || !(b[q] > a[q])) return PSN_EINVAL;
-    if (!psn_size_supported(n)) return PSN_ESIZE;
+    for (int q = 0; q < 3; ++q)
+        if (!psn_size_supported(n3[q])) return PSN_ESIZE;
     psn_plan* p = new (std::nothrow) psn_plan();
     if (!p) return PSN_ENOMEM;
-    p->n = n;
+    p->n = n3[0];
     p->tol = tol;
     p->dtype = dtype;
+    p->general = !(n3[0] == n3[1] && n3[1] == n3[2]);
+    if (p->general) p->sched24 = p->sched3 = -1;  // the five-step path has no tile schedules
     double lam = 0.0, dmin = 1e300, diag2 = 0.0;
     for (int q = 0; q < 3; ++q) {
         const double w = b[q] - a[q];
+        p->ng[q] = n3[q];
         p->a[q] = a[q];
         p->b[q] = b[q];
-        p->h[q] = w / (n - 1);
-        p->T[q] = n * p->h[q];
-        p->period[q] = 2.0 * n * p->h[q];
+        p->h[q] = w / (n3[q] - 1);
+        p->T[q] = n3[q] * p->h[q];
+        p->period[q] = 2.0 * n3[q] * p->h[q];
         lam = std::fmax(lam, 0.5 * w);
-        dmin = std::fmin(dmin, w / (50.0 * n));
+        dmin = std::fmin(dmin, w / (50.0 * n3[q]));
         diag2 += w * w;
     }
     p->L = lam;
@@ -394,6 +425,12 @@ psn_status psn_plan_create_box(int n, const double* a, const double* b, double t
     }
     *out = p;
     return PSN_OK;
+}
+
+psn_status psn_plan_create_box(int n, const double* a, const double* b, double tol, psn_dtype dtype,
+                               psn_plan** out) {
+    const int n3[3] = {n, n, n};
+    return psn_plan_create_grid(n3, a, b, tol, dtype, out);
 }
 
 psn_status psn_plan_create(int n, double L, double tol, psn_dtype dtype, psn_plan** out) {
@@ -417,14 +454,24 @@ psn_status psn_kernel_build(psn_plan* p, void* stream) {
     psn_status st = PSN_OK;
     const size_t cxb = p->dtype == PSN_F32 ? 8 : 16;
     const size_t wb = p->dtype == PSN_SPLIT ? 8 : psn_host::elem_bytes(p->dtype);
-    if ((st = dev_alloc(&p->K, (n + 1) * (n + 1) * n * kb, &tot)) ||
-        (st = dev_alloc(&p->Kb, (n + 1) * (n + 1) * kb, &tot)) || (st = dev_alloc(&p->tw, M * cxb, &tot)) ||
-        (st = dev_alloc(&p->W1, n * n * n * wb, &tot)) ||
-        (st = dev_alloc(&p->W2, psn_host::w2_elems(p->n) * wb, &tot))) {
+    if (p->general) {
+        // plain octant, per-axis twiddle tables of 4 n_q entries, plain workspaces
+        const size_t g0 = p->ng[0], g1 = p->ng[1], g2 = p->ng[2];
+        if ((st = dev_alloc(&p->K, (g0 + 1) * (g1 + 1) * (g2 + 1) * kb, &tot)) ||
+            (st = dev_alloc(&p->Kb, kb, &tot)) || (st = dev_alloc(&p->tw, 4 * (g0 + g1 + g2) * cxb, &tot)) ||
+            (st = dev_alloc(&p->W1, general_w1(p) * general_cx(p), &tot)) ||
+            (st = dev_alloc(&p->W2, general_w2(p) * general_cx(p), &tot))) {
+            free_device(p);
+            return st;
+        }
+    } else if ((st = dev_alloc(&p->K, (n + 1) * (n + 1) * n * kb, &tot)) ||
+               (st = dev_alloc(&p->Kb, (n + 1) * (n + 1) * kb, &tot)) || (st = dev_alloc(&p->tw, M * cxb, &tot)) ||
+               (st = dev_alloc(&p->W1, n * n * n * wb, &tot)) ||
+               (st = dev_alloc(&p->W2, psn_host::w2_elems(p->n) * wb, &tot))) {
         free_device(p);
         return st;
     }
-    if (p->dtype == PSN_SPLIT) {
+    if (p->dtype == PSN_SPLIT && !p->general) {
         if ((st = dev_alloc(&p->W1lo, n * n * n * 4, &tot)) ||
             (st = dev_alloc(&p->W2lo, psn_host::w2_elems(p->n) * 4, &tot))) {
             free_device(p);
@@ -433,13 +480,23 @@ psn_status psn_kernel_build(psn_plan* p, void* stream) {
     }
     p->device_bytes = tot;
 
-    // twiddles exp(-2 pi i m / M), evaluated in extended precision, rounded once
-    std::vector<double> twd(2 * M);
-    for (size_t m = 0; m < M; ++m) {
-        const long double a = 2.0L * 3.14159265358979323846264338327950288L * (long double)m / (long double)M;
-        twd[2 * m] = (double)cosl(a);
-        twd[2 * m + 1] = (double)-sinl(a);
+    // twiddles exp(-2 pi i m / M), evaluated in extended precision, rounded
+    // once; a grid with per-axis sizes has one table of 4 n_q entries per axis
+    // (the padded length 2 n_q needs exp(-2 pi i m / 4 n_q))
+    std::vector<double> twd;
+    auto table = [&](size_t len) {
+        for (size_t m = 0; m < len; ++m) {
+            const long double a = 2.0L * 3.14159265358979323846264338327950288L * (long double)m / (long double)len;
+            twd.push_back((double)cosl(a));
+            twd.push_back((double)-sinl(a));
+        }
+    };
+    if (p->general) {
+        for (int q = 0; q < 3; ++q) table(4 * size_t(p->ng[q]));
+    } else {
+        table(M);
     }
+    const size_t tw_entries = twd.size() / 2;
     std::vector<float> twf;
     const void* twsrc = twd.data();
     if (p->dtype == PSN_F32) {
@@ -452,7 +509,10 @@ psn_status psn_kernel_build(psn_plan* p, void* stream) {
 
     DevBuf d_tau, d_w, d_gl, d_A, d_c;
     if ((st = dev_alloc(&d_tau.p, terms * 8, &tot)) || (st = dev_alloc(&d_w.p, terms * 8, &tot)) ||
-        (st = dev_alloc(&d_gl.p, 32 * 8, &tot)) || (st = dev_alloc(&d_A.p, psn_host::kbuild_scratch_doubles(p->n, terms) * 8, &tot)) ||
+        (st = dev_alloc(&d_gl.p, 32 * 8, &tot)) || (st = dev_alloc(&d_A.p,
+                                  psn_host::kbuild_scratch_doubles(std::max(p->ng[0], std::max(p->ng[1], p->ng[2])),
+                                                                   terms) * 8,
+                                  &tot)) ||
         (st = dev_alloc(&d_c.p, 2 * 8, &tot))) {
         free_device(p);
         return st;
@@ -461,7 +521,7 @@ psn_status psn_kernel_build(psn_plan* p, void* stream) {
     std::memcpy(gl.data(), glx, sizeof glx);
     std::memcpy(gl.data() + 16, glw, sizeof glw);
     double cc[2] = {0, 0};
-    bool ok = hip_ok(hipMemcpyAsync(p->tw, twsrc, M * cxb, hipMemcpyHostToDevice, s), "copy twiddles") &&
+    bool ok = hip_ok(hipMemcpyAsync(p->tw, twsrc, tw_entries * cxb, hipMemcpyHostToDevice, s), "copy twiddles") &&
               hip_ok(hipMemcpyAsync(d_tau.p, p->tau.data(), terms * 8, hipMemcpyHostToDevice, s), "copy tau") &&
               hip_ok(hipMemcpyAsync(d_w.p, p->w.data(), terms * 8, hipMemcpyHostToDevice, s), "copy w") &&
               hip_ok(hipMemcpyAsync(d_gl.p, gl.data(), 32 * 8, hipMemcpyHostToDevice, s), "copy nodes");
@@ -484,6 +544,7 @@ psn_status psn_kernel_build(psn_plan* p, void* stream) {
         return PSN_EDEVICE;
     }
     p->built = true;
+    if (p->general) return PSN_OK;  // no tile schedules on the five-step path
     return tune_schedule(p, s);
 }
 
@@ -780,6 +841,7 @@ psn_status psn_plan_query(const psn_plan* p, psn_plan_info* info) {
     info->tuned = p->tuned ? 1 : 0;
     info->device = p->built ? p->device : -1;
     info->correction = p->correction;
+    for (int q = 0; q < 3; ++q) info->n3[q] = p->ng[q];
     for (int q = 0; q < 3; ++q) {
         info->a[q] = p->a[q];
         info->b[q] = p->b[q];
@@ -801,13 +863,15 @@ psn_status psn_plan_query(const psn_plan* p, psn_plan_info* info) {
 
 psn_status psn_plan_set_correction(psn_plan* p, int mode) {
     if (!p || (mode != PSN_CORRECTION_FOLDED && mode != PSN_CORRECTION_FOURIER)) return PSN_EINVAL;
+    if (p->general && mode != PSN_CORRECTION_FOLDED) return PSN_EINVAL;
     if (p->built) return PSN_ESTATE;
     p->correction = mode;
     return PSN_OK;
 }
 
 psn_status psn_plan_set_schedule(psn_plan* p, int p24, int p3) {
-    if (!p || p24 < 0 || p24 >= psn_host::kScheduleCandidates || p3 < 0 || p3 >= psn_host::kScheduleCandidates)
+    if (!p || p->general || p24 < 0 || p24 >= psn_host::kScheduleCandidates || p3 < 0 ||
+        p3 >= psn_host::kScheduleCandidates)
         return PSN_EINVAL;
     p->sched24 = p24;
     p->sched3 = p3;
@@ -829,6 +893,18 @@ psn_status psn_plan_gs_table(const psn_plan* p, double* tau, double* w, int cap,
 psn_status psn_kernel_download(const psn_plan* p, double* octant) {
     if (!p || !octant) return PSN_EINVAL;
     if (!p->built) return PSN_ESTATE;
+    if (p->general) {
+        const size_t g0 = p->ng[0], g1 = p->ng[1], g2 = p->ng[2];
+        const size_t cnt = (g0 + 1) * (g1 + 1) * (g2 + 1);
+        const size_t kb = psn_host::kernel_elem_bytes(p->dtype);
+        std::vector<unsigned char> hk(cnt * kb);
+        if (!hip_ok(hipMemcpy(hk.data(), p->K, hk.size(), hipMemcpyDeviceToHost), "copy K")) return PSN_EDEVICE;
+        const double inv = 8.0 * double(g0) * g1 * g2;
+        for (size_t i = 0; i < cnt; ++i)
+            octant[i] = (kb == 4 ? (double)reinterpret_cast<const float*>(hk.data())[i]
+                                 : reinterpret_cast<const double*>(hk.data())[i]) * inv;
+        return PSN_OK;
+    }
     const size_t n = p->n, np1 = n + 1;
     const size_t kb = psn_host::kernel_elem_bytes(p->dtype);
     std::vector<unsigned char> hk(np1 * np1 * n * kb), hb(np1 * np1 * kb);

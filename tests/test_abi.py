@@ -189,3 +189,30 @@ def test_correction_option_host_checks():
     assert p.info()["correction"] == psn.CORRECTION_FOURIER
     q = psn.Plan(16, 1.0, 1e-12, "f32", correction="fourier")
     assert q.info()["correction"] == psn.CORRECTION_FOURIER
+
+
+def test_grid_plan_host_checks():
+    lib = psn._lib
+    P = ctypes.c_void_p
+    h = P()
+    a = (ctypes.c_double * 3)(-1, -1, -1)
+    b = (ctypes.c_double * 3)(1, 2, 3)
+    for bad, st in (((16, 24, 14), -2), ((16, 0, 32), -2), ((7, 16, 16), -2)):
+        nn = (ctypes.c_int * 3)(*bad)
+        assert lib.psn_plan_create_grid(nn, a, b, 1e-12, 1, ctypes.byref(h)) == st
+    assert lib.psn_plan_create_grid(None, a, b, 1e-12, 1, ctypes.byref(h)) == -1
+    p = psn.Plan((16, 24, 32), box=((-1, -1, -1), (1, 2, 3)), tol=1e-12, dtype="f64")
+    info = p.info()
+    assert info["n3"] == (16, 24, 32)
+    g = O.geometry(W.Box((-1, -1, -1), (1, 2, 3), (16, 24, 32)))
+    for q in range(3):
+        assert info["h3"][q] == pytest.approx(g.h[q], rel=1e-15)
+        assert info["T3"][q] == pytest.approx(g.T[q], rel=1e-15)
+    assert info["delta"] == pytest.approx(g.delta, rel=1e-15)
+    assert info["R"] == pytest.approx(g.R, rel=1e-15)
+    tau_o, _, _ = O.gaussian_sum(1e-12, g.delta, g.R)
+    assert info["terms"] == tau_o.size
+    with pytest.raises(psn.PsnError):
+        p.set_schedule(0, 0)
+    assert lib.psn_plan_set_correction(p.handle, psn.CORRECTION_FOURIER) == -1
+    assert info["algorithmic_bytes"] == 2 * 8 * 16 * 24 * 32 + 24 * 8 * 16 * 24 * 33 + 8 * 17 * 25 * 33

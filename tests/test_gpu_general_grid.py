@@ -1,0 +1,86 @@
+"""Grids with a different number of points per axis (psn_plan_create_grid:
+the paper's general box with N = n0 n1 n2 points) against the oracle, whose
+padded convolution and kernel spectrum take per-axis sizes directly."""
+import numpy as np
+import pytest
+
+import oracle as O
+import workloads as W
+from gpu_common import TOL, max_rel, torch_cuda
+
+pytestmark = pytest.mark.gpu
+psn = pytest.importorskip("paper_1612_01799_amd")
+
+CASES = [((16, 24, 32), (-2.0, -2.5, -3.0), (2.0, 2.5, 3.0)),
+         ((32, 16, 48), (-3.0, -2.0, -1.0), (2.0, 3.5, 5.0)),
+         ((48, 64, 12), (-2.0, -2.0, -1.0), (2.0, 2.0, 1.0)),
+         ((64, 96, 160), (-3.0, -4.0, -6.0), (3.0, 4.0, 6.0)),
+         ((162, 8, 24), (-4.0, -1.0, -1.5), (4.0, 1.0, 1.5))]
+
+
+def _case(n3, a, b, seed):
+    box = W.Box(a, b, n3)
+    c = box.centre()
+    half = min(0.5 * (b[q] - a[q]) for q in range(3))
+    mix = W.draw_mixture(seed, 4, -0.2 * half, 0.2 * half, 0.15 * half, 0.3 * half, 0.5, 1.5, box)
+    mix.centres = mix.centres + np.asarray(c)[None, :]
+    return box, W.mixture_density(mix)
+
+
+@pytest.mark.parametrize("case", CASES, ids=["x".join(map(str, c[0])) for c in CASES])
+@pytest.mark.parametrize("dtype", ["f64", "f32", "split"])
+def test_general_grid_matches_oracle(case, dtype):
+    torch = torch_cuda()
+    n3, a, b = case
+    box, rho = _case(n3, a, b, sum(n3))
+    ks = O.kernel_spectrum(box, 1e-12)
+    ref = O.solve(rho, O.half_spectrum(ks))
+    plan = psn.Plan(n3, box=(a, b), tol=1e-12, dtype=dtype).build()
+    info = plan.info()
+    assert info["n3"] == n3
+    r = torch.from_numpy(rho).to("cuda", plan.io_dtype())
+    u = plan.solve(r)
+    torch.cuda.synchronize()
+    err = max_rel(u.double().cpu().numpy(), ref)
+    print(f"grid {n3} {dtype}: {err:.3e}", flush=True)
+    assert err <= TOL[dtype]
+    if dtype != "f32":
+        K = plan.kernel_octant()
+        assert K.shape == tuple(v + 1 for v in n3)
+        assert np.max(np.abs(K - ks.octant)) <= 1e-13 * abs(ks.octant[0, 0, 0])
+
+
+def test_general_grid_in_place_timed_and_batched():
+    torch = torch_cuda()
+    n3, a, b = CASES[1]
+    box, rho = _case(n3, a, b, 11)
+    ref = O.solve(rho, O.half_spectrum(O.kernel_spectrum(box, 1e-12)))
+    plan = psn.Plan(n3, box=(a, b), tol=1e-12, dtype="f64").build()
+    r = torch.from_numpy(rho).to("cuda")
+    out = torch.empty_like(r)
+    ms = plan.solve_timed(r, out)
+    assert np.all(ms >= 0) and max_rel(out.cpu().numpy(), ref) <= TOL["f64"]
+    c = r.clone()
+    plan.solve(c, out=c)
+    torch.cuda.synchronize()
+    assert max_rel(c.cpu().numpy(), ref) <= TOL["f64"]
+    # beside a cube plan, in both batched entry points
+    cube = psn.Plan(32, 2.5, 1e-12, "f64").build()
+    rc_np = W.mixture_density(W.draw_mixture(12, 4, -0.8, 0.8, 0.4, 0.7, 0.5, 1.5, W.Box.cube(2.5, 32)))
+    rc = torch.from_numpy(rc_np).to("cuda")
+    refc = O.solve(rc_np, O.half_spectrum(O.kernel_spectrum(W.Box.cube(2.5, 32), 1e-12)))
+    outs = psn.solve_batched([plan, cube, plan], [r, rc, r])
+    outs2 = [torch.empty_like(x) for x in (r, rc, r)]
+    psn.solve_batched_noalloc([plan, cube, plan], [r, rc, r], outs2)
+    torch.cuda.synchronize()
+    for u, u2, rf in zip(outs, outs2, (ref, refc, ref)):
+        assert max_rel(u.cpu().numpy(), rf) <= TOL["f64"]
+        assert torch.equal(u, u2)
+
+
+def test_equal_sizes_give_the_cube_plan():
+    torch_cuda()
+    p = psn.Plan((32, 32, 32), box=((-2, -2, -2), (2, 2, 2)), tol=1e-12, dtype="f32").build()
+    q = psn.Plan(32, 2.0, 1e-12, "f32").build()
+    assert p.info()["schedule"] == q.info()["schedule"]
+    assert np.array_equal(p.kernel_octant(), q.kernel_octant())
