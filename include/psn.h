@@ -39,8 +39,9 @@ typedef struct psn_plan psn_plan;
  *   PSN_F64   FP64 arithmetic and FP64 storage everywhere.
  *   PSN_F32   FP32 arithmetic, FP32 storage, FP32 kernel spectrum.
  *   PSN_SPLIT FP64 arithmetic inside each pass; intermediates between passes
- *             stored as an FP32 high part plus a bfloat16 low part (6 bytes per
- *             real); FP64 kernel spectrum; FP64 input and output. */
+ *             stored in 6 bytes per real, split into the high 32-bit word of
+ *             the FP64 value and the next 16 bits (the value rounded to 37
+ *             significant bits); FP64 kernel spectrum; FP64 input and output. */
 typedef enum { PSN_F64 = 0, PSN_F32 = 1, PSN_SPLIT = 2 } psn_dtype;
 
 /* How the near-zone correction I_delta ~ C0 rho + (C2/6) Laplace(rho) enters

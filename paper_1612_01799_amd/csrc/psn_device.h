@@ -721,12 +721,6 @@ struct Prec<DT_SPLIT> {
     using Kt = double;
 };
 
-__device__ __forceinline__ uint32_t f32_to_bf16_rne(float f) {
-    uint32_t u = __float_as_uint(f);
-    u += 0x7FFFu + ((u >> 16) & 1u);
-    return u >> 16;
-}
-__device__ __forceinline__ float bf16_to_f32(uint32_t b) { return __uint_as_float(b << 16); }
 
 // Workspace of complex values between passes.
 template <int DT>
@@ -754,6 +748,7 @@ __device__ __forceinline__ double gld(const double* p) { return *(const PSN_GLOB
 // two consecutive complex floats in one 16-byte access (p 16-byte aligned)
 typedef float psn_f4 __attribute__((ext_vector_type(4)));
 typedef uint32_t psn_u2 __attribute__((ext_vector_type(2)));
+typedef uint32_t psn_u4 __attribute__((ext_vector_type(4)));
 __device__ __forceinline__ void gst2(cx<float>* p, cx<float> a, cx<float> b) {
     *(PSN_GLOBAL psn_f4*)(p) = psn_f4{a.x, a.y, b.x, b.y};
 }
@@ -839,55 +834,54 @@ struct Work<DT_F64> {
         b = gld(p + i + 1);
     }
 };
-// FP32 high part + bfloat16 low part (two per 32-bit word): 6 bytes per real.
+// FP64 values in 6 bytes per real: each real rounded to its leading 48 bits
+// (sign, exponent and 36 fraction bits: 37 significant bits, half an ulp of
+// 2^-37 relative).  A complex value is one 12-byte element of three 32-bit
+// words: the high words of the real and imaginary parts, then both parts'
+// next 16 bits, so one access per lane moves a whole element.  Unpacking is
+// a shift and a mask; no float conversions.
+typedef uint32_t psn_u3 __attribute__((ext_vector_type(3)));
 template <>
 struct Work<DT_SPLIT> {
-    cx<float>* hi;
-    uint32_t* lo;
-    static __device__ __forceinline__ cx<double> join(cx<float> h, uint32_t l) {
-        return {double(h.x) + double(bf16_to_f32(l & 0xFFFFu)), double(h.y) + double(bf16_to_f32(l >> 16))};
+    uint32_t* p;  // 3 words per element
+    static __device__ __forceinline__ psn_u3 pack(cx<double> v) {
+        // + 2^15 rounds the kept 48 bits to nearest (a carry may reach the exponent)
+        const uint64_t bx = uint64_t(__double_as_longlong(v.x)) + 0x8000u;
+        const uint64_t by = uint64_t(__double_as_longlong(v.y)) + 0x8000u;
+        return psn_u3{uint32_t(bx >> 32), uint32_t(by >> 32), (uint32_t(bx) >> 16) | (uint32_t(by) & 0xFFFF0000u)};
     }
-    static __device__ __forceinline__ uint32_t low_of(cx<double> v, cx<float> h) {
-        const float lx = float(v.x - double(h.x)), ly = float(v.y - double(h.y));
-        return uint32_t(f32_to_bf16_rne(lx) | (f32_to_bf16_rne(ly) << 16));
+    static __device__ __forceinline__ cx<double> join(psn_u3 w) {
+        return {__longlong_as_double((long long)((uint64_t(w.x) << 32) | uint64_t(w.z << 16))),
+                __longlong_as_double((long long)((uint64_t(w.y) << 32) | uint64_t(w.z & 0xFFFF0000u)))};
     }
-    __device__ __forceinline__ cx<double> ld(size_t i) const { return join(gld(hi + i), gld(lo + i)); }
-    __device__ __forceinline__ void st(size_t i, cx<double> v) const {
-        const cx<float> h{float(v.x), float(v.y)};
-        gst(hi + i, h);
-        gst(lo + i, low_of(v, h));
-    }
+    static __device__ __forceinline__ psn_u3 ld3(const uint32_t* q) { return *(const PSN_GLOBAL psn_u3*)(q); }
+    static __device__ __forceinline__ void st3(uint32_t* q, psn_u3 w) { *(PSN_GLOBAL psn_u3*)(q) = w; }
+    __device__ __forceinline__ cx<double> ld(size_t i) const { return join(ld3(p + 3 * i)); }
+    __device__ __forceinline__ void st(size_t i, cx<double> v) const { st3(p + 3 * i, pack(v)); }
     __device__ __forceinline__ cx<double> ld(size_t ub, uint32_t off) const {
-        return join(gld(byte_off(sbase(hi + ub), off * 8u)), gld(byte_off(sbase(lo + ub), off * 4u)));
+        return join(ld3(byte_off(sbase(p + 3 * ub), off * 12u)));
     }
     __device__ __forceinline__ void st(size_t ub, uint32_t off, cx<double> v) const {
-        const cx<float> h{float(v.x), float(v.y)};
-        gst(byte_off(sbase(hi + ub), off * 8u), h);
-        gst(byte_off(sbase(lo + ub), off * 4u), low_of(v, h));
+        st3(byte_off(sbase(p + 3 * ub), off * 12u), pack(v));
     }
+    // elements i and i+1
     __device__ __forceinline__ void st2(size_t i, cx<double> a, cx<double> b) const {
-        const cx<float> ha{float(a.x), float(a.y)}, hb{float(b.x), float(b.y)};
-        gst2(hi + i, ha, hb);
-        *(PSN_GLOBAL psn_u2*)(lo + i) = psn_u2{low_of(a, ha), low_of(b, hb)};
+        st3(p + 3 * i, pack(a));
+        st3(p + 3 * i + 3, pack(b));
     }
-    // elements ub + off and ub + off + 1 (ub + off even): one 16-byte high
-    // access and one 8-byte low access
     __device__ __forceinline__ void ld_pair(size_t ub, uint32_t off, cx<double>& a, cx<double>& b) const {
-        const psn_f4 h = *(const PSN_GLOBAL psn_f4*)(byte_off(sbase(hi + ub), off * 8u));
-        const psn_u2 l = *(const PSN_GLOBAL psn_u2*)(byte_off(sbase(lo + ub), off * 4u));
-        a = join({h.x, h.y}, l.x);
-        b = join({h.z, h.w}, l.y);
+        const uint32_t* q = byte_off(sbase(p + 3 * ub), off * 12u);
+        a = join(ld3(q));
+        b = join(ld3(q + 3));
     }
     __device__ __forceinline__ void st_pair(size_t ub, uint32_t off, cx<double> a, cx<double> b) const {
-        const cx<float> ha{float(a.x), float(a.y)}, hb{float(b.x), float(b.y)};
-        *(PSN_GLOBAL psn_f4*)(byte_off(sbase(hi + ub), off * 8u)) = psn_f4{ha.x, ha.y, hb.x, hb.y};
-        *(PSN_GLOBAL psn_u2*)(byte_off(sbase(lo + ub), off * 4u)) = psn_u2{low_of(a, ha), low_of(b, hb)};
+        uint32_t* q = byte_off(sbase(p + 3 * ub), off * 12u);
+        st3(q, pack(a));
+        st3(q + 3, pack(b));
     }
     __device__ __forceinline__ void ld_pair(size_t i, cx<double>& a, cx<double>& b) const {
-        const psn_f4 h = *(const PSN_GLOBAL psn_f4*)(hi + i);
-        const psn_u2 l = *(const PSN_GLOBAL psn_u2*)(lo + i);
-        a = join({h.x, h.y}, l.x);
-        b = join({h.z, h.w}, l.y);
+        a = join(ld3(p + 3 * i));
+        b = join(ld3(p + 3 * i + 3));
     }
 };
 

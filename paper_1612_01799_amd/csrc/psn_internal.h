@@ -32,8 +32,6 @@ struct psn_plan {
     void* tw = nullptr;   // 2n twiddles exp(-2 pi i m / 2n), compute precision
     void* W1 = nullptr;   // n * n * n complex
     void* W2 = nullptr;   // n * 2n * n complex
-    void* W1lo = nullptr; // SPLIT low parts
-    void* W2lo = nullptr;
     size_t device_bytes = 0;
     // schedule of the strided passes (candidate indices, see Sched)
     int sched24 = 0, sched3 = 0;
@@ -82,8 +80,6 @@ struct Slot {
     void* u;
     void* W1;
     void* W2;
-    void* W1lo;
-    void* W2lo;
 };
 
 // Enqueue the passes for `count` slots that share n and precision (one launch
@@ -124,7 +120,8 @@ hipError_t launch_kernel_build(psn_plan* p, const double* d_tau, const double* d
                                const double* d_glx, const double* d_glw, double* d_A, double* d_c,
                                hipStream_t stream);
 
-size_t elem_bytes(psn_dtype dt);        // bytes of one complex intermediate in the main array
+size_t elem_bytes(psn_dtype dt);        // bytes of one complex value in the compute precision (8 or 16)
+size_t work_bytes(psn_dtype dt);        // bytes of one stored complex intermediate (8, 16, or 12 split)
 size_t kernel_elem_bytes(psn_dtype dt); // bytes of one real of the kernel spectrum
 bool size_compiled(int n);
 

@@ -1215,7 +1215,9 @@ struct Sched {
     // an odd factor: with the chains exchanged one at a time); one row with
     // the chains exchanged one at a time; and (odd factor) half the elements
     // per thread, or (powers of two) 4 elements per thread with the one-chain
-    // exchange
+    // exchange.  (The whole layout tile of 8 columns with the one-chain
+    // exchange fits one 512-thread FP64-arithmetic workgroup per CU and
+    // measured 30 % slower at n = 512.)
     static constexpr TileV v3[psn_host::kScheduleCandidates] = {
         d3,
         pick_tile3(N, odd > 1 ? TileV{C::BP3, C::T3, 2, true} : TileV{C::BP3, C::T3, 2}, d3, C::CX, C::BS),
@@ -1475,8 +1477,8 @@ Prob<DT> prob_of(const psn_host::Slot& sl) {
     pr.rho = static_cast<const Io*>(sl.rho);
     pr.u = static_cast<Io*>(sl.u);
     if constexpr (DT == DT_SPLIT) {
-        pr.w1 = {static_cast<cx<float>*>(sl.W1), static_cast<uint32_t*>(sl.W1lo)};
-        pr.w2 = {static_cast<cx<float>*>(sl.W2), static_cast<uint32_t*>(sl.W2lo)};
+        pr.w1 = {static_cast<uint32_t*>(sl.W1)};
+        pr.w2 = {static_cast<uint32_t*>(sl.W2)};
     } else {
         pr.w1 = {static_cast<cx<Real>*>(sl.W1)};
         pr.w2 = {static_cast<cx<Real>*>(sl.W2)};
@@ -1553,7 +1555,7 @@ template <int DT>
 hipError_t tune_plan(const psn_plan* p, hipStream_t s, int* best24, int* best3) {
     Batch<DT> bt{};
     bt.count = 1;
-    bt.p[0] = prob_of<DT>(psn_host::Slot{p, nullptr, nullptr, p->W1, p->W2, p->W1lo, p->W2lo});
+    bt.p[0] = prob_of<DT>(psn_host::Slot{p, nullptr, nullptr, p->W1, p->W2});
     switch (p->n) {
 #define PSN_CASE(NN) \
     case NN: return tune_n<NN, DT>(bt, s, best24, best3);

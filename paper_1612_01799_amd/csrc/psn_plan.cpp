@@ -135,7 +135,7 @@ psn_status dev_alloc(void** ptr, size_t bytes, size_t* total) {
 }
 
 void free_device(psn_plan* p) {
-    for (void** q : {&p->K, &p->Kb, &p->tw, &p->W1, &p->W2, &p->W1lo, &p->W2lo}) {
+    for (void** q : {&p->K, &p->Kb, &p->tw, &p->W1, &p->W2}) {
         if (*q) (void)hipFree(*q);
         *q = nullptr;
     }
@@ -240,35 +240,25 @@ size_t general_cx(const psn_plan* p) { return p->dtype == PSN_F32 ? 8 : 16; }
 size_t slot_bytes(const psn_plan* p) {
     if (p->general) return align256(general_w1(p) * general_cx(p)) + align256(general_w2(p) * general_cx(p));
     const size_t n3 = size_t(p->n) * p->n * p->n;
-    const size_t wb = p->dtype == PSN_SPLIT ? 8 : psn_host::elem_bytes(p->dtype);
+    const size_t wb = psn_host::work_bytes(p->dtype);
     const size_t w2 = psn_host::w2_elems(p->n);
-    size_t b = align256(n3 * wb) + align256(w2 * wb);
-    if (p->dtype == PSN_SPLIT) b += align256(n3 * 4) + align256(w2 * 4);
-    return b;
+    return align256(n3 * wb) + align256(w2 * wb);
 }
 
 psn_host::Slot own_slot(const psn_plan* p, const void* rho, void* u) {
-    return psn_host::Slot{p, rho, u, p->W1, p->W2, p->W1lo, p->W2lo};
+    return psn_host::Slot{p, rho, u, p->W1, p->W2};
 }
 
 psn_host::Slot arena_slot(const psn_plan* p, const void* rho, void* u, char* base) {
     const size_t n3 = size_t(p->n) * p->n * p->n;
-    const size_t wb = p->dtype == PSN_SPLIT ? 8 : psn_host::elem_bytes(p->dtype);
-    psn_host::Slot sl{p, rho, u, nullptr, nullptr, nullptr, nullptr};
+    psn_host::Slot sl{p, rho, u, nullptr, nullptr};
     if (p->general) {
         sl.W1 = base;
         sl.W2 = base + align256(general_w1(p) * general_cx(p));
         return sl;
     }
     sl.W1 = base;
-    base += align256(n3 * wb);
-    sl.W2 = base;
-    base += align256(psn_host::w2_elems(p->n) * wb);
-    if (p->dtype == PSN_SPLIT) {
-        sl.W1lo = base;
-        base += align256(n3 * 4);
-        sl.W2lo = base;  // sized by w2_elems as well
-    }
+    sl.W2 = base + align256(n3 * psn_host::work_bytes(p->dtype));
     return sl;
 }
 
@@ -374,6 +364,7 @@ bool size_compiled(int n) {
 }
 
 size_t elem_bytes(psn_dtype dt) { return dt == PSN_F64 ? 16 : 8; }
+size_t work_bytes(psn_dtype dt) { return dt == PSN_F64 ? 16 : dt == PSN_SPLIT ? 12 : 8; }
 size_t kernel_elem_bytes(psn_dtype dt) { return dt == PSN_F32 ? 4 : 8; }
 
 }  // namespace psn_host
@@ -453,7 +444,7 @@ psn_status psn_kernel_build(psn_plan* p, void* stream) {
     size_t tot = 0;
     psn_status st = PSN_OK;
     const size_t cxb = p->dtype == PSN_F32 ? 8 : 16;
-    const size_t wb = p->dtype == PSN_SPLIT ? 8 : psn_host::elem_bytes(p->dtype);
+    const size_t wb = psn_host::work_bytes(p->dtype);
     if (p->general) {
         // plain octant, per-axis twiddle tables of 4 n_q entries, plain workspaces
         const size_t g0 = p->ng[0], g1 = p->ng[1], g2 = p->ng[2];
@@ -470,13 +461,6 @@ psn_status psn_kernel_build(psn_plan* p, void* stream) {
                (st = dev_alloc(&p->W2, psn_host::w2_elems(p->n) * wb, &tot))) {
         free_device(p);
         return st;
-    }
-    if (p->dtype == PSN_SPLIT && !p->general) {
-        if ((st = dev_alloc(&p->W1lo, n * n * n * 4, &tot)) ||
-            (st = dev_alloc(&p->W2lo, psn_host::w2_elems(p->n) * 4, &tot))) {
-            free_device(p);
-            return st;
-        }
     }
     p->device_bytes = tot;
 
