@@ -74,26 +74,68 @@ def pass_bytes(n, dtype):
             (2 * bs + bio) * n3]
 
 
-def measured_traffic(n, kernel):
-    """HBM bytes per launch of `kernel` from the committed rocprofv3 PMC summary,
-    or None if there is none for this size or the kernel sources changed since."""
+def _sources_digest():
     import hashlib
-    path = os.path.join(ROOT, "profiles", f"solve_n{n}_f32_hbm_traffic.txt")
-    if kernel != "P3_fwd_mulK_inv_axis0" or not os.path.exists(path):
-        return None
     try:
         src = b"".join(open(os.path.join(ROOT, "paper_1612_01799_amd", "csrc", f), "rb").read()
                        for f in KERNEL_SOURCES)
     except OSError:
         return None
-    digest = hashlib.sha256(src).hexdigest()[:16]
-    total, recorded = None, None
+    return hashlib.sha256(src).hexdigest()[:16]
+
+
+def _profile_value(path, row_prefix, column):
+    """Value of `column` in the row starting with `row_prefix` of a committed
+    profile summary, or None if absent or recorded for other kernel sources."""
+    if not os.path.exists(path):
+        return None
+    digest, recorded, header, value = _sources_digest(), None, None, None
     for line in open(path):
         if line.startswith("# kernel sources sha256[:16]"):
             recorded = line.split(":")[-1].strip()
-        if line.startswith(f"psn::p3_conv<{n}, 1,"):
-            total = float(line.split()[-3]) * 1e9
-    return total if (total is not None and recorded == digest) else None
+        elif line.startswith("kernel "):
+            header = line.split()
+        elif header and line.startswith(row_prefix):
+            fields = line[len(row_prefix):].split()
+            # the kernel name may hold spaces: count columns from the right
+            value = float(fields[len(fields) - (len(header) - header.index(column))])
+    return value if (value is not None and recorded == digest) else None
+
+
+def measured_traffic(n, kernel):
+    """HBM bytes per launch of the middle pass from the committed rocprofv3 PMC
+    summary (copy-calibrated FETCH_SIZE + WRITE_SIZE), or None if there is none
+    for this size or the kernel sources changed since it was taken."""
+    if kernel != "P3_fwd_mulK_inv_axis0":
+        return None
+    v = _profile_value(os.path.join(ROOT, "profiles", f"solve_n{n}_f32_hbm_traffic.txt"),
+                       f"psn::p3p_conv<{n}, 1,", "total_GB")
+    return None if v is None else v * 1e9
+
+
+def measured_valu(n, kernel):
+    """VALU wave-instructions per launch of the middle pass from the committed
+    rocprofv3 counter summary (SQ_INSTS_VALU), or None (as measured_traffic)."""
+    if kernel != "P3_fwd_mulK_inv_axis0":
+        return None
+    return _profile_value(os.path.join(ROOT, "profiles", f"solve_n{n}_f32_valu_counters.txt"),
+                          f"psn::p3p_conv<{n}, 1,", "valu_insts")
+
+
+# VALU issue peak: each of the 256 CUs issues one wave64 VALU instruction per
+# cycle (4 SIMDs, one every 4 cycles each) at the 2.4 GHz peak clock
+VALU_PEAK = 256 * 2.4e9
+
+
+def alu_roofline(n, kernel, avg_ms):
+    """The dominant kernel against its second roof: VALU instruction issue."""
+    insts = measured_valu(n, kernel)
+    if insts is None:
+        return None
+    rate = insts / (avg_ms * 1e-3)
+    return {"bound": "alu", "kernel": kernel, "achieved": rate / 1e9, "peak": VALU_PEAK / 1e9,
+            "unit": "G wave64 VALU instructions/s", "frac": rate / VALU_PEAK, "valu_insts_per_launch": insts,
+            "avg_ms": float(avg_ms)}
 
 
 def time_path(psn, torch, n, L, dtype, rho64, steps, warmup):
@@ -382,6 +424,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": desc, "n": n, "padded": 2 * n, "path": "f32", "tol": 1e-12,
                    "schedule": list(info32["schedule"]), "tuned": bool(info32["tuned"])},
+        "roofline_alu": alu_roofline(n, PASS_NAMES[dom], passes[dom]),
         "roofline": {"bound": "hbm", "kernel": PASS_NAMES[dom], "achieved": achieved / 1e9, "peak": HBM_PEAK / 1e9,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK, "traffic": measured_traffic(n, PASS_NAMES[dom]),
                      "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE/WRITE_SIZE, copy-calibrated)",
