@@ -2,8 +2,8 @@
  * psn.h -- C ABI of the MI355X free-space Poisson solver.
  *
  * Computes u = U * rho with U(x) = 1/(4 pi |x|) on a box (the cube [-L, L]^3 or
- * a general [a0,b0] x [a1,b1] x [a2,b2]) sampled with n points per axis (both
- * end points included, h_q = (b_q - a_q)/(n-1)), by the
+ * a general [a0,b0] x [a1,b1] x [a2,b2]) sampled with n points per axis, or n_q
+ * points on axis q (both end points included, h_q = (b_q - a_q)/(n_q - 1)), by the
  * method of Exl, "A GPU accelerated and error-controlled solver for the
  * unbounded Poisson equation in three dimensions" (arXiv 1612.01799):
  *
@@ -16,7 +16,8 @@
  * spectrum that never materialise its zero half.
  *
  * Conventions shared by every entry point
- *   - Arrays are C order [i0][i1][i2] (i2 contiguous) of n^3 reals.
+ *   - Arrays are C order [i0][i1][i2] (i2 contiguous) of n^3 reals (n0 n1 n2
+ *     for a plan from psn_plan_create_grid).
  *   - rho and u are DEVICE pointers owned by the caller.  F32 plans read and
  *     write float; F64 and SPLIT plans read and write double.
  *   - `stream` is a hipStream_t (NULL = the legacy default stream).  Solves are
@@ -54,7 +55,8 @@ typedef enum { PSN_F64 = 0, PSN_F32 = 1, PSN_SPLIT = 2 } psn_dtype;
  *                           and one backward FFT of size N = n^3 (section 3),
  *                           added after the padded convolution with the
  *                           G-tensor alone.
- * For a resolved density the two agree to rounding. */
+ * For a resolved density the two agree far below the method's error (about
+ * 1e-13 of max |u| for a Gaussian of width 1 on a 32^3 grid). */
 typedef enum { PSN_CORRECTION_FOLDED = 0, PSN_CORRECTION_FOURIER = 1 } psn_correction;
 
 typedef enum {
@@ -172,8 +174,8 @@ psn_status psn_solve_batched(int count, psn_plan *const *plans,
  * batch as psn_solve_batched, with the same results, but it allocates
  * nothing.  The workspace of every entry comes from one fixed device array of
  * 256 MiB per device, compiled into the library and held until the process
- * ends (e.g. two n = 160 FP32 entries or ten n = 96 ones fit; one entry needs
- * about 24 n^3 bytes in FP32, 48 n^3 in F64 and SPLIT).  No graph is captured:
+ * ends (e.g. two n = 160 FP32 entries or twelve n = 96 ones fit; one entry
+ * needs about 24 n^3 bytes in FP32, 36 n^3 in SPLIT and 48 n^3 in F64).  No graph is captured:
  * the launches are enqueued on `stream` directly, entries of one
  * (n, precision, schedule) sharing each launch, under the schedule that
  * psn_solve_batched timed for such a group if it did (else the plans').  plans, rho, u as for
@@ -205,7 +207,8 @@ psn_status psn_plan_set_schedule(psn_plan *p, int p24, int p3);
  * psn_kernel_build, since the kernel spectrum differs.  With
  * PSN_CORRECTION_FOURIER a solve also runs the size-N transform pair; its
  * workspace is the plan's (or the batch entry's) own.
- * Errors: PSN_EINVAL (bad mode), PSN_ESTATE (already built). */
+ * Errors: PSN_EINVAL (bad mode, or PSN_CORRECTION_FOURIER on a plan from
+ * psn_plan_create_grid with unequal sizes), PSN_ESTATE (already built). */
 psn_status psn_plan_set_correction(psn_plan *p, int mode);
 
 /* Fill *info: the discretisation and error-control parameters of the paper's
