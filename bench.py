@@ -68,10 +68,13 @@ def oracle_workers():
 
 
 def pass_bytes(n, dtype):
-    bio, bs, bk = {"f32": (4, 4, 4), "f64": (8, 8, 8), "split": (8, 6, 8)}[dtype]
+    """Algorithmic bytes of P1..P5: each array read and written once.  b1, b2:
+    bytes of one complex element of W1 (n^3) and W2 (2 n^3); split precision
+    keeps W1 in 12-byte elements and W2 in FP64."""
+    bio, b1, b2, bk = {"f32": (4, 8, 8, 4), "f64": (8, 16, 16, 8), "split": (8, 12, 16, 8)}[dtype]
     n3 = float(n) ** 3
-    return [(bio + 2 * bs) * n3, 6 * bs * n3, 8 * bs * n3 + bk * (n + 1.0) ** 3, 6 * bs * n3,
-            (2 * bs + bio) * n3]
+    return [(bio + b1) * n3, (b1 + 2 * b2) * n3, 4 * b2 * n3 + bk * (n + 1.0) ** 3, (2 * b2 + b1) * n3,
+            (b1 + bio) * n3]
 
 
 def _sources_digest():

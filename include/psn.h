@@ -39,10 +39,11 @@ typedef struct psn_plan psn_plan;
 /* Arithmetic of a plan.
  *   PSN_F64   FP64 arithmetic and FP64 storage everywhere.
  *   PSN_F32   FP32 arithmetic, FP32 storage, FP32 kernel spectrum.
- *   PSN_SPLIT FP64 arithmetic inside each pass; intermediates between passes
- *             stored in 6 bytes per real, split into the high 32-bit word of
- *             the FP64 value and the next 16 bits (the value rounded to 37
- *             significant bits); FP64 kernel spectrum; FP64 input and output. */
+ *   PSN_SPLIT FP64 arithmetic inside each pass; the axis-2/axis-1
+ *             intermediate stored in 6 bytes per real, split into the high
+ *             32-bit word of the FP64 value and the next 16 bits (the value
+ *             rounded to 37 significant bits); the axis-1/axis-0 intermediate
+ *             in FP64; FP64 kernel spectrum; FP64 input and output. */
 typedef enum { PSN_F64 = 0, PSN_F32 = 1, PSN_SPLIT = 2 } psn_dtype;
 
 /* How the near-zone correction I_delta ~ C0 rho + (C2/6) Laplace(rho) enters
@@ -175,7 +176,7 @@ psn_status psn_solve_batched(int count, psn_plan *const *plans,
  * nothing.  The workspace of every entry comes from one fixed device array of
  * 256 MiB per device, compiled into the library and held until the process
  * ends (e.g. two n = 160 FP32 entries or twelve n = 96 ones fit; one entry
- * needs about 24 n^3 bytes in FP32, 36 n^3 in SPLIT and 48 n^3 in F64).  No graph is captured:
+ * needs about 24 n^3 bytes in FP32, 44 n^3 in SPLIT and 48 n^3 in F64).  No graph is captured:
  * the launches are enqueued on `stream` directly, entries of one
  * (n, precision, schedule) sharing each launch, under the schedule that
  * psn_solve_batched timed for such a group if it did (else the plans').  plans, rho, u as for

@@ -121,7 +121,8 @@ hipError_t launch_kernel_build(psn_plan* p, const double* d_tau, const double* d
                                hipStream_t stream);
 
 size_t elem_bytes(psn_dtype dt);        // bytes of one complex value in the compute precision (8 or 16)
-size_t work_bytes(psn_dtype dt);        // bytes of one stored complex intermediate (8, 16, or 12 split)
+size_t w1_bytes(psn_dtype dt);          // bytes of one complex element of W1 (8, 16, or 12 split)
+size_t w2_bytes(psn_dtype dt);          // bytes of one complex element of W2 (8, or 16: split keeps W2 in FP64)
 size_t kernel_elem_bytes(psn_dtype dt); // bytes of one real of the kernel spectrum
 bool size_compiled(int n);
 

@@ -172,11 +172,21 @@ struct Cfg {
 // graph); workgroup units are numbered problem-major.
 constexpr int kMaxBatch = kMaxBatchHost;
 
+// Storage of the axis-1 output W2: split precision keeps it in FP64.  The
+// middle pass reads and writes W2 in narrow column tiles at large strides,
+// where 12-byte elements straddle the memory's 64-byte sectors; W1, moved in
+// whole tile runs by the axis passes, keeps the 12-byte form.
+template <int DT>
+constexpr int w2_dt() {
+    return DT == DT_SPLIT ? DT_F64 : DT;
+}
+
 template <int DT>
 struct Prob {
     const typename Prec<DT>::Io* rho;
     typename Prec<DT>::Io* u;
-    Work<DT> w1, w2;
+    Work<DT> w1;
+    Work<w2_dt<DT>()> w2;
     const typename Prec<DT>::Kt* K;
     const typename Prec<DT>::Kt* Kb;
     const cx<typename Prec<DT>::Real>* tw;
@@ -308,7 +318,7 @@ p2_fwd(const Batch<DT> bt) {
     if (ug >= bt.count * units) return;
     const Prob<DT>& P = bt.p[ug / units];
     const Work<DT>& w1 = P.w1;
-    const Work<DT>& w2 = P.w2;
+    const auto& w2 = P.w2;
     const cx<Real>* __restrict__ tw = P.tw;
     const int u = ug % units;
     const int i0 = u / tiles, tile = u % tiles;
@@ -409,7 +419,7 @@ p3_conv(const Batch<DT> bt) {
     const int ug = xcd_unit();
     if (ug >= bt.count * units) return;  // whole workgroup
     const Prob<DT>& P = bt.p[ug / units];
-    const Work<DT>& w2 = P.w2;
+    const auto& w2 = P.w2;
     const typename C::Kt* __restrict__ K = P.K;
     const cx<Real>* __restrict__ tw = P.tw;
     const int u = ug % units;
@@ -538,7 +548,7 @@ p3_col0(const Batch<DT> bt) {
 
     if (int(blockIdx.x) >= bt.count * G0::groups) return;
     const Prob<DT>& P = bt.p[blockIdx.x / G0::groups];
-    const Work<DT>& w2 = P.w2;
+    const auto& w2 = P.w2;
     const typename C::Kt* __restrict__ K = P.K;
     const typename C::Kt* __restrict__ Kb = P.Kb;
     const cx<Real>* __restrict__ tw = P.tw;
@@ -612,7 +622,7 @@ p4_inv(const Batch<DT> bt) {
     if (ug >= bt.count * units) return;
     const Prob<DT>& P = bt.p[ug / units];
     const Work<DT>& w1 = P.w1;
-    const Work<DT>& w2 = P.w2;
+    const auto& w2 = P.w2;
     const cx<Real>* __restrict__ tw = P.tw;
     const int u = ug % units;
     const int i0 = u / tiles, tile = u % tiles;
@@ -666,7 +676,7 @@ p2p_fwd(const Batch<DT> bt) {
     if (ug >= bt.count * units) return;
     const Prob<DT>& P = bt.p[ug / units];
     const Work<DT>& w1 = P.w1;
-    const Work<DT>& w2 = P.w2;
+    const auto& w2 = P.w2;
     const cx<Real>* __restrict__ tw = P.tw;
     const int u = ug % units;
     const int pr = u / tiles, tile = u % tiles;
@@ -782,7 +792,7 @@ p3p_conv(const Batch<DT> bt) {
     const int ug = xcd_unit();
     if (ug >= bt.count * units) return;  // whole workgroup
     const Prob<DT>& P = bt.p[ug / units];
-    const Work<DT>& w2 = P.w2;
+    const auto& w2 = P.w2;
     const typename C::Kt* __restrict__ K = P.K;
     const cx<Real>* __restrict__ tw = P.tw;
     const int u = ug % units;
@@ -901,7 +911,7 @@ p4p_inv(const Batch<DT> bt) {
     if (ug >= bt.count * units) return;
     const Prob<DT>& P = bt.p[ug / units];
     const Work<DT>& w1 = P.w1;
-    const Work<DT>& w2 = P.w2;
+    const auto& w2 = P.w2;
     const cx<Real>* __restrict__ tw = P.tw;
     const int u = ug % units;
     const int pr = u / tiles, tile = u % tiles;
@@ -1478,7 +1488,7 @@ Prob<DT> prob_of(const psn_host::Slot& sl) {
     pr.u = static_cast<Io*>(sl.u);
     if constexpr (DT == DT_SPLIT) {
         pr.w1 = {static_cast<uint32_t*>(sl.W1)};
-        pr.w2 = {static_cast<uint32_t*>(sl.W2)};
+        pr.w2 = {static_cast<cx<double>*>(sl.W2)};
     } else {
         pr.w1 = {static_cast<cx<Real>*>(sl.W1)};
         pr.w2 = {static_cast<cx<Real>*>(sl.W2)};

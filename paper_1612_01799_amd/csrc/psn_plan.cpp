@@ -212,8 +212,6 @@ psn_status tune_schedule(psn_plan* p, hipStream_t s) {
 
 size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
 
-// workspace bytes of one solve: W1 (n^3 complex), W2 (2 n^3 complex), and the
-// low parts of the split format
 // HBM bytes one solve must move: five passes, each one read and one write of
 // its arrays (io: rho and u, s: complex intermediates per real, k: kernel
 // spectrum per real)
@@ -227,9 +225,11 @@ double algorithmic_bytes(const psn_plan* p) {
         const double n0 = p->ng[0], n1 = p->ng[1], n2 = p->ng[2];
         return 2 * bio * n0 * n1 * n2 + 24 * bs * n0 * n1 * (n2 + 1) + bk * (n0 + 1) * (n1 + 1) * (n2 + 1);
     }
+    // W1 (n^3 complex) is written and read twice (P1, P2, P4, P5), W2 (2 n^3
+    // complex) four times (P2, P3 read and write, P4)
     const double n3 = double(p->n) * p->n * p->n, np1 = p->n + 1.0;
-    const double bs = p->dtype == PSN_F32 ? 4 : (p->dtype == PSN_F64 ? 8 : 6);
-    return 2 * bio * n3 + 24 * bs * n3 + bk * np1 * np1 * np1;
+    const double b1 = double(psn_host::w1_bytes(p->dtype)), b2 = double(psn_host::w2_bytes(p->dtype));
+    return 2 * bio * n3 + 4 * b1 * n3 + 8 * b2 * n3 + bk * np1 * np1 * np1;
 }
 
 // complex workspace elements of a grid with per-axis sizes
@@ -240,9 +240,8 @@ size_t general_cx(const psn_plan* p) { return p->dtype == PSN_F32 ? 8 : 16; }
 size_t slot_bytes(const psn_plan* p) {
     if (p->general) return align256(general_w1(p) * general_cx(p)) + align256(general_w2(p) * general_cx(p));
     const size_t n3 = size_t(p->n) * p->n * p->n;
-    const size_t wb = psn_host::work_bytes(p->dtype);
     const size_t w2 = psn_host::w2_elems(p->n);
-    return align256(n3 * wb) + align256(w2 * wb);
+    return align256(n3 * psn_host::w1_bytes(p->dtype)) + align256(w2 * psn_host::w2_bytes(p->dtype));
 }
 
 psn_host::Slot own_slot(const psn_plan* p, const void* rho, void* u) {
@@ -258,7 +257,7 @@ psn_host::Slot arena_slot(const psn_plan* p, const void* rho, void* u, char* bas
         return sl;
     }
     sl.W1 = base;
-    sl.W2 = base + align256(n3 * psn_host::work_bytes(p->dtype));
+    sl.W2 = base + align256(n3 * psn_host::w1_bytes(p->dtype));
     return sl;
 }
 
@@ -364,7 +363,8 @@ bool size_compiled(int n) {
 }
 
 size_t elem_bytes(psn_dtype dt) { return dt == PSN_F64 ? 16 : 8; }
-size_t work_bytes(psn_dtype dt) { return dt == PSN_F64 ? 16 : dt == PSN_SPLIT ? 12 : 8; }
+size_t w1_bytes(psn_dtype dt) { return dt == PSN_F64 ? 16 : dt == PSN_SPLIT ? 12 : 8; }
+size_t w2_bytes(psn_dtype dt) { return dt == PSN_F32 ? 8 : 16; }
 size_t kernel_elem_bytes(psn_dtype dt) { return dt == PSN_F32 ? 4 : 8; }
 
 }  // namespace psn_host
@@ -444,7 +444,6 @@ psn_status psn_kernel_build(psn_plan* p, void* stream) {
     size_t tot = 0;
     psn_status st = PSN_OK;
     const size_t cxb = p->dtype == PSN_F32 ? 8 : 16;
-    const size_t wb = psn_host::work_bytes(p->dtype);
     if (p->general) {
         // plain octant, per-axis twiddle tables of 4 n_q entries, plain workspaces
         const size_t g0 = p->ng[0], g1 = p->ng[1], g2 = p->ng[2];
@@ -457,8 +456,8 @@ psn_status psn_kernel_build(psn_plan* p, void* stream) {
         }
     } else if ((st = dev_alloc(&p->K, (n + 1) * (n + 1) * n * kb, &tot)) ||
                (st = dev_alloc(&p->Kb, (n + 1) * (n + 1) * kb, &tot)) || (st = dev_alloc(&p->tw, M * cxb, &tot)) ||
-               (st = dev_alloc(&p->W1, n * n * n * wb, &tot)) ||
-               (st = dev_alloc(&p->W2, psn_host::w2_elems(p->n) * wb, &tot))) {
+               (st = dev_alloc(&p->W1, n * n * n * psn_host::w1_bytes(p->dtype), &tot)) ||
+               (st = dev_alloc(&p->W2, psn_host::w2_elems(p->n) * psn_host::w2_bytes(p->dtype), &tot))) {
         free_device(p);
         return st;
     }

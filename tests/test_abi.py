@@ -130,9 +130,11 @@ def test_solve_before_build_is_a_state_error():
 
 def test_algorithmic_bytes():
     n = 512
-    for dt, (bio, bs, bk) in {"f32": (4, 4, 4), "f64": (8, 8, 8), "split": (8, 6, 8)}.items():
+    # W1: n^3 complex, written and read twice; W2: 2 n^3 complex, accessed four
+    # times; split precision stores W1 in 12 bytes and W2 in FP64
+    for dt, (bio, b1, b2, bk) in {"f32": (4, 8, 8, 4), "f64": (8, 16, 16, 8), "split": (8, 12, 16, 8)}.items():
         info = psn.Plan(n, 12.0, 1e-12, dt).info()
-        assert info["algorithmic_bytes"] == 2 * bio * n ** 3 + 24 * bs * n ** 3 + bk * (n + 1) ** 3
+        assert info["algorithmic_bytes"] == 2 * bio * n ** 3 + 4 * b1 * n ** 3 + 8 * b2 * n ** 3 + bk * (n + 1) ** 3
 
 
 def test_schedule_override_validation():
