@@ -13,6 +13,7 @@
 #include <mutex>
 #include <new>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "psn_internal.h"
@@ -53,18 +54,31 @@ double erfcinv(double y) {
     return x;
 }
 
-// max over log-spaced r in [delta, R] of |4 pi r U_GS(r) - 1|
+// max over log-spaced r in [delta, R] of |4 pi r U_GS(r) - 1|.  The radii are
+// split over a few host threads; each radius is summed the same way whoever
+// takes it, and a maximum does not depend on the order, so the result is the
+// same for any thread count.
 double gs_max_rel_error(const std::vector<double>& tau, const std::vector<double>& w, double delta, double R,
                         int points) {
-    double worst = 0.0;
     const double a = std::log(delta), b = std::log(R);
-    for (int i = 0; i < points; ++i) {
-        const double r = std::exp(a + (b - a) * i / (points - 1));
-        double s = 0.0;
-        for (size_t j = 0; j < tau.size(); ++j) s += w[j] * std::exp(-(tau[j] * r) * (tau[j] * r));
-        worst = std::fmax(worst, std::fabs(4.0 * kPi * r * s - 1.0));
-    }
-    return worst;
+    auto part = [&](int i0, int i1) {
+        double worst = 0.0;
+        for (int i = i0; i < i1; ++i) {
+            const double r = std::exp(a + (b - a) * i / (points - 1));
+            double s = 0.0;
+            for (size_t j = 0; j < tau.size(); ++j) s += w[j] * std::exp(-(tau[j] * r) * (tau[j] * r));
+            worst = std::fmax(worst, std::fabs(4.0 * kPi * r * s - 1.0));
+        }
+        return worst;
+    };
+    const int nt = int(std::max(1u, std::min(8u, std::thread::hardware_concurrency())));
+    std::vector<double> worst(nt, 0.0);
+    std::vector<std::thread> pool;
+    for (int k = 1; k < nt; ++k)
+        pool.emplace_back([&, k] { worst[k] = part(int(long(points) * k / nt), int(long(points) * (k + 1) / nt)); });
+    worst[0] = part(0, int(long(points) / nt));
+    for (auto& th : pool) th.join();
+    return *std::max_element(worst.begin(), worst.end());
 }
 
 // Gaussian sum by sinc quadrature of 1/r = (2/sqrt(pi)) int exp(-r^2 e^{2t} + t) dt
