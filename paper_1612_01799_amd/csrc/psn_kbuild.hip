@@ -17,7 +17,9 @@
 // * otherwise: composite 16-point Gauss-Legendre of the integral itself, with
 //   one panel per two half periods of cos(kappa_k y) plus eight.
 // The octant assembly is the product of the (k0, k1) rows sum_j over the
-// terms with the (k2) columns: a register-tiled FP64 GEMM.  On a cube the
+// terms with the (k2) columns: an FP64 GEMM on the matrix cores
+// (v_mfma_f64_16x16x4f64, the row operand a_j(k0) a_j(k1) formed as it is
+// fed).  On a cube the
 // three axes share one mode table and K is symmetric in (k0, k1); then only
 // k0 <= k1 is computed, the pair product a_j(k0) a_j(k1) is formed first (so
 // both halves agree bitwise) and each value is written to both places.
@@ -29,6 +31,8 @@
 namespace psn {
 
 constexpr double kPi = 3.14159265358979323846;
+
+typedef double psn_d4 __attribute__((ext_vector_type(4)));
 
 constexpr int kMoments = 22;  // series terms of the tau T < 1 branch: 1/22! < 1e-21
 
@@ -219,7 +223,7 @@ __global__ void k_edge(const double* __restrict__ A0, const double* __restrict__
 // stream through LDS in chunks of 16: a_j(k0) and w_j a_j(k2).  With SYM
 // (A0 == A1) only tiles with k0b <= k1 run and entries with k0 <= k1 are
 // written, to (k0, k1) and (k1, k0).
-constexpr int kTile0 = 128, kTile2 = 64, kChunk = 16;
+constexpr int kTile0 = 128, kTile2 = 64, kChunk = 32;
 
 template <class Kt, bool SYM>
 __global__ void __launch_bounds__(256) k_gemm(const double* __restrict__ A0, const double* __restrict__ A1,
@@ -233,12 +237,15 @@ __global__ void __launch_bounds__(256) k_gemm(const double* __restrict__ A0, con
     const int k1 = blockIdx.z;
     const int k0b = blockIdx.y * kTile0, k2b = blockIdx.x * kTile2;
     if (SYM && k0b > k1) return;  // whole workgroup: the mirror tile covers it
-    const int tid = threadIdx.x, q = tid % 8, r = tid / 8;
-    double acc[4][8];
+    const int tid = threadIdx.x;
+    // wave wv owns rows k0b + 32 wv .. +31 as two 16-row blocks, all 64 columns
+    // as four 16-column blocks: eight 16 x 16 FP64 accumulators
+    const int wv = tid / 64, lane = tid % 64, li = lane % 16, lg = lane / 16;
+    psn_d4 acc[2][4];
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int i = 0; i < 2; ++i)
 #pragma unroll
-        for (int c = 0; c < 8; ++c) acc[i][c] = 0.0;
+        for (int c = 0; c < 4; ++c) acc[i][c] = psn_d4{0.0, 0.0, 0.0, 0.0};
     for (int j0 = 0; j0 < terms; j0 += kChunk) {
         __syncthreads();  // the previous chunk's reads are done
         for (int idx = tid; idx < kChunk * kTile0; idx += 256) {
@@ -251,34 +258,40 @@ __global__ void __launch_bounds__(256) k_gemm(const double* __restrict__ A0, con
         }
         if (tid < kChunk) s1[tid] = j0 + tid < terms ? A1[size_t(j0 + tid) * np1 + k1] : 0.0;
         __syncthreads();
-#pragma unroll 2
-        for (int jj = 0; jj < kChunk; ++jj) {
+        // four k-steps of four terms: lane (li, lg) gives term 4 s + lg of row
+        // li (the product a_j(k0) a_j(k1)) and of column li (w_j a_j(k2))
+#pragma unroll
+        for (int st = 0; st < kChunk / 4; ++st) {
+            const int jj = 4 * st + lg;
             const double a1 = s1[jj];
-            double p[4], b[8];
+            double av[2], bv[4];
 #pragma unroll
-            for (int i = 0; i < 4; ++i) p[i] = sa[jj][r + 32 * i] * a1;
+            for (int i = 0; i < 2; ++i) av[i] = sa[jj][32 * wv + 16 * i + li] * a1;
 #pragma unroll
-            for (int c = 0; c < 8; ++c) b[c] = sb[jj][q + 8 * c];
+            for (int c = 0; c < 4; ++c) bv[c] = sb[jj][16 * c + li];
 #pragma unroll
-            for (int i = 0; i < 4; ++i)
+            for (int i = 0; i < 2; ++i)
 #pragma unroll
-                for (int c = 0; c < 8; ++c) acc[i][c] = fma(p[i], b[c], acc[i][c]);
+                for (int c = 0; c < 4; ++c) acc[i][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[i], bv[c], acc[i][c], 0, 0, 0);
         }
     }
+    // result (row lg + 4 e, column li) of each 16 x 16 block is word e of the
+    // lane (the FP64 form interleaves the rows over the four lane groups)
     const double C0 = Cc[0], C2 = Cc[1];
     const double b1 = 2.0 * kPi * k1 / p1;
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        const int k0 = k0b + r + 32 * i;
+    for (int ie = 0; ie < 8; ++ie) {
+        const int i = ie / 4, e = ie % 4;
+        const int k0 = k0b + 32 * wv + 16 * i + lg + 4 * e;
         if (k0 > n || (SYM && k0 > k1)) continue;
         const double b0 = 2.0 * kPi * k0 / p0;
         const double q01 = b0 * b0 + b1 * b1;
 #pragma unroll
-        for (int c = 0; c < 8; ++c) {
-            const int k2 = k2b + q + 8 * c;
+        for (int c = 0; c < 4; ++c) {
+            const int k2 = k2b + 16 * c + li;
             if (k2 >= n) continue;
             const double b2 = 2.0 * kPi * k2 / p2;
-            const double v = acc[i][c] + fold * (C0 - (C2 / 6.0) * (q01 + b2 * b2));
+            const double v = acc[i][c][e] + fold * (C0 - (C2 / 6.0) * (q01 + b2 * b2));
             if (k2 == 0) {
                 const double e = Kn[size_t(k1) * np1 + k0];
                 K[psn_host::k_index(n, k1, k0, 0)] = Kt(scale * 0.5 * (v + e));
