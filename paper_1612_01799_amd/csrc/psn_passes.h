@@ -1024,8 +1024,12 @@ p5_c2r(const Batch<DT> bt) {
 // with the Laplacian's symbol -sum_q kappa_q^2, kappa_q = 2 pi k / (n h_q) at
 // the signed index k (period n h_q, the samples' own grid).  It runs after
 // the axis-1 inverse, while rho is intact (also in place) and W2 is free: z
-// lives in W2's memory, as n^3 complex values in C order, and is added to u
-// after the axis-2 pass.
+// lives in W2's memory, as n^3 complex values in C order.  Five line passes,
+// each one read and one write of the volume: axis 2 forward reading rho
+// itself; axis 1 forward; axis 0 forward, times the symbol
+// (C0 - (C2/6) |kappa|^2) / n^3, inverse (one pass, radices reversed as in
+// the middle pass of the solve); axis 1 inverse; and, after the solve's
+// axis-2 pass, axis 2 inverse adding Re z to u.
 template <int DT>
 struct CorrProb {
     const typename Prec<DT>::Io* rho;
@@ -1041,50 +1045,13 @@ struct CorrBatch {
     CorrProb<DT> p[kMaxBatch];
 };
 
-// z = rho + 0i (elementwise; blockIdx.y = problem)
-template <int N, int DT>
-__global__ void corr_load(const CorrBatch<DT> cb) {
-    const CorrProb<DT>& P = cb.p[blockIdx.y];
-    using Real = typename Prec<DT>::Real;
-    constexpr size_t n3 = size_t(N) * N * N;
-    for (size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n3; i += size_t(gridDim.x) * blockDim.x)
-        gst(P.z + i, cx<Real>{Real(P.rho[i]), Real(0)});
-}
-
-// z *= (C0 - (C2/6) |kappa|^2) / n^3
-template <int N, int DT>
-__global__ void corr_symbol(const CorrBatch<DT> cb) {
-    const CorrProb<DT>& P = cb.p[blockIdx.y];
-    using Real = typename Prec<DT>::Real;
-    constexpr size_t n3 = size_t(N) * N * N;
-    const double inv = 1.0 / double(n3);
-    for (size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n3; i += size_t(gridDim.x) * blockDim.x) {
-        const int k[3] = {int(i / (size_t(N) * N)), int((i / N) % N), int(i % N)};
-        double q = 0.0;
-#pragma unroll
-        for (int a = 0; a < 3; ++a) {
-            const double kap = P.kq[a] * double(k[a] <= N / 2 ? k[a] : k[a] - N);
-            q += kap * kap;
-        }
-        const Real f = Real((P.c0 - P.c2 * q) * inv);
-        gst(P.z + i, scale(gld(P.z + i), f));
-    }
-}
-
-// u += Re z
-template <int N, int DT>
-__global__ void corr_add(const CorrBatch<DT> cb) {
-    const CorrProb<DT>& P = cb.p[blockIdx.y];
-    using Io = typename Prec<DT>::Io;
-    constexpr size_t n3 = size_t(N) * N * N;
-    for (size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n3; i += size_t(gridDim.x) * blockDim.x)
-        P.u[i] = Io(P.u[i] + Io(gld(P.z + i).x));
-}
-
 // Length-N transforms of z along axis AX (DIR = -1 forward, +1 inverse,
 // unnormalised).  Axis 2: a workgroup holds LC contiguous lines, one LDS row
-// each.  Axes 0 and 1: a workgroup holds B adjacent lines (consecutive i2),
-// element-major in LDS, so each point's B values are one contiguous run.
+// each; the forward reads rho (real) instead of z, the inverse adds the real
+// part of its result to u instead of storing z.  Axes 0 and 1: a workgroup
+// holds B adjacent lines (consecutive i2), element-major in LDS, so each
+// point's B values are one contiguous run; on axis 0 the forward is followed
+// in registers by the symbol and the inverse (DIR is ignored there).
 template <int N, int DT>
 struct CorrCfg {
     using Real = typename Prec<DT>::Real;
@@ -1109,17 +1076,28 @@ __global__ void corr_fft(const CorrBatch<DT> cb) {
     cx<Real>* __restrict__ z = P.z;
     cx<Real> d[F::E];
     if constexpr (AX == 2) {
+        using Io = typename Prec<DT>::Io;
         const int t = threadIdx.x % CC::T, ln = threadIdx.x / CC::T;
         const size_t base = (size_t(blockIdx.x) * CC::LC + ln) * N;
         TwLds<Real> tl{sb + CC::LC * CC::NP};
         tl.fill(P.tw, N, threadIdx.x, CC::LC * CC::T);
         __syncthreads();
 #pragma unroll
-        for (int e = 0; e < F::E; ++e) d[e] = gld(z + base + F::in_pos(t, e));
+        for (int e = 0; e < F::E; ++e) {
+            if constexpr (DIR < 0) d[e] = {Real(P.rho[base + F::in_pos(t, e)]), Real(0)};
+            else d[e] = gld(z + base + F::in_pos(t, e));
+        }
         LdsRows<Real> lds{sb + ln * CC::NP};
         F::run1(d, t, tl, lds);
 #pragma unroll
-        for (int e = 0; e < F::E; ++e) gst(z + base + F::out_pos(t, e), d[e]);
+        for (int e = 0; e < F::E; ++e) {
+            if constexpr (DIR < 0) {
+                gst(z + base + F::out_pos(t, e), d[e]);
+            } else {
+                Io* __restrict__ u = P.u + base + F::out_pos(t, e);
+                *u = Io(*u + Io(d[e].x));
+            }
+        }
     } else {
         constexpr int B = CC::B;
         const int c = threadIdx.x % B, t = threadIdx.x / B;
@@ -1134,38 +1112,53 @@ __global__ void corr_fft(const CorrBatch<DT> cb) {
         for (int e = 0; e < F::E; ++e) d[e] = gld(z + base + size_t(F::in_pos(t, e)) * stride);
         LdsCols<Real> lds{sb, B, c};
         F::run1(d, t, tl, lds);
+        if constexpr (AX == 0) {
+            // z *= (C0 - (C2/6) |kappa|^2) / n^3 at (k0, k1 = line, k2 = i2), then the
+            // inverse with the radices reversed, which starts from this layout
+            using Fi = TeamFFT<N, CC::T, Real, +1, true>;
+            auto kap2 = [](double kq, int k) {
+                const double v = kq * double(k <= N / 2 ? k : k - N);
+                return v * v;
+            };
+            const double q12 = kap2(P.kq[1], line) + kap2(P.kq[2], i2);
+            const double inv = 1.0 / (double(N) * N * N);
 #pragma unroll
-        for (int e = 0; e < F::E; ++e) gst(z + base + size_t(F::out_pos(t, e)) * stride, d[e]);
+            for (int e = 0; e < F::E; ++e) {
+                const double q = q12 + kap2(P.kq[0], F::out_pos(t, e));
+                d[e] = scale(d[e], Real((P.c0 - P.c2 * q) * inv));
+            }
+            __syncthreads();  // the forward's last exchange reads are done
+            Fi::run1(d, t, tl, lds);
+#pragma unroll
+            for (int e = 0; e < F::E; ++e) gst(z + base + size_t(Fi::out_pos(t, e)) * stride, d[e]);
+        } else {
+#pragma unroll
+            for (int e = 0; e < F::E; ++e) gst(z + base + size_t(F::out_pos(t, e)) * stride, d[e]);
+        }
     }
 }
 
+// The correction's passes before the solve's axis-2 pass (z after the
+// axis-1 inverse) and the one after it (axis-2 inverse added to u).
 template <int N, int DT>
-hipError_t launch_corr_fft_all(const CorrBatch<DT>& cb, hipStream_t s, bool forward) {
+hipError_t launch_corr_z(const CorrBatch<DT>& cb, hipStream_t s) {
     using CC = CorrCfg<N, DT>;
     const size_t lds2 = (size_t(CC::LC) * CC::NP + TwLds<typename CC::Real>::slots(N)) * CC::CX;
     const size_t lds01 = (size_t(CC::B) * N + TwLds<typename CC::Real>::slots(N)) * CC::CX;
     const dim3 g2(N * N / CC::LC, cb.count), g01(N * (N / CC::B), cb.count);
     const dim3 b2(CC::LC * CC::T), b01(CC::B * CC::T);
-    if (forward) {
-        hipLaunchKernelGGL((corr_fft<N, DT, 2, -1>), g2, b2, lds2, s, cb);
-        hipLaunchKernelGGL((corr_fft<N, DT, 1, -1>), g01, b01, lds01, s, cb);
-        hipLaunchKernelGGL((corr_fft<N, DT, 0, -1>), g01, b01, lds01, s, cb);
-    } else {
-        hipLaunchKernelGGL((corr_fft<N, DT, 0, +1>), g01, b01, lds01, s, cb);
-        hipLaunchKernelGGL((corr_fft<N, DT, 1, +1>), g01, b01, lds01, s, cb);
-        hipLaunchKernelGGL((corr_fft<N, DT, 2, +1>), g2, b2, lds2, s, cb);
-    }
+    hipLaunchKernelGGL((corr_fft<N, DT, 2, -1>), g2, b2, lds2, s, cb);
+    hipLaunchKernelGGL((corr_fft<N, DT, 1, -1>), g01, b01, lds01, s, cb);
+    hipLaunchKernelGGL((corr_fft<N, DT, 0, -1>), g01, b01, lds01, s, cb);
+    hipLaunchKernelGGL((corr_fft<N, DT, 1, +1>), g01, b01, lds01, s, cb);
     return hipGetLastError();
 }
-
 template <int N, int DT>
-hipError_t launch_corr_z(const CorrBatch<DT>& cb, hipStream_t s) {
-    const dim3 g(1024, cb.count), b(256);
-    hipLaunchKernelGGL((corr_load<N, DT>), g, b, 0, s, cb);
-    hipError_t e = launch_corr_fft_all<N, DT>(cb, s, true);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((corr_symbol<N, DT>), g, b, 0, s, cb);
-    return launch_corr_fft_all<N, DT>(cb, s, false);
+hipError_t launch_corr_add(const CorrBatch<DT>& cb, hipStream_t s) {
+    using CC = CorrCfg<N, DT>;
+    const size_t lds2 = (size_t(CC::LC) * CC::NP + TwLds<typename CC::Real>::slots(N)) * CC::CX;
+    hipLaunchKernelGGL((corr_fft<N, DT, 2, +1>), dim3(N * N / CC::LC, cb.count), dim3(CC::LC * CC::T), lds2, s, cb);
+    return hipGetLastError();
 }
 
 // ------------------------------------------------------------------ launcher
@@ -1426,7 +1419,7 @@ hipError_t solve_n(const Batch<DT>& bt, hipStream_t s, hipEvent_t* ev, int v24, 
     mark(4);
     if (cb && (e = launch_corr_z<N, DT>(*cb, s)) != hipSuccess) return e;
     hipLaunchKernelGGL((p5_c2r<N, DT>), dim3(xcd_grid(cnt * N * N / C::LC)), dim3(C::LC * C::T), lds_rows, s, bt);
-    if (cb) hipLaunchKernelGGL((corr_add<N, DT>), dim3(1024, cb->count), dim3(256), 0, s, *cb);
+    if (cb && (e = launch_corr_add<N, DT>(*cb, s)) != hipSuccess) return e;
     mark(5);
     return hipGetLastError();
 }
