@@ -241,6 +241,51 @@ def bench_size(psn, torch, np, n, steps, warmup, with_oracle):
     return out
 
 
+def _timed_solves(torch, plan, rho, out, steps, warmup):
+    for _ in range(warmup):
+        plan.solve(rho, out)
+    torch.cuda.synchronize()
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    t0.record()
+    for _ in range(steps):
+        plan.solve(rho, out)
+    t1.record()
+    torch.cuda.synchronize()
+    return t0.elapsed_time(t1) / steps
+
+
+def bench_options(psn, torch, np, rho64, steps, warmup):
+    """The plan options beyond the cube path, on the benchmark box's spacing:
+    a grid with per-axis sizes (512 x 512 x 384, FP32) and the n = 512 solve
+    with the near-zone correction by its Fourier series instead of folded."""
+    import workloads as W
+    out = {}
+    n3, h = (512, 512, 384), 24.0 / 511
+    a = tuple(-0.5 * h * (q - 1) for q in n3)
+    b = tuple(0.5 * h * (q - 1) for q in n3)
+    box = W.Box(a, b, n3)
+    half = min(b)
+    mix = W.draw_mixture(1006, 64, -0.5 * half, 0.5 * half, 0.3, 2.0, 0.5, 1.5, box)
+    plan = psn.Plan(n3, box=(a, b), tol=1e-12, dtype="f32").build()
+    rho = torch.from_numpy(W.mixture_density(mix)).to("cuda", torch.float32)
+    u = torch.empty_like(rho)
+    ms = _timed_solves(torch, plan, rho, u, steps, warmup)
+    out["grid_per_axis"] = {
+        "workload": "512 x 512 x 384 grid, h = 24/511, 64-Gaussian seeded mixture (seed 1006), FP32",
+        "ms": ms, "value": float(np.prod(n3)) / (ms * 1e-3),
+        "hbm_frac": plan.info()["algorithmic_bytes"] / (ms * 1e-3) / HBM_PEAK}
+    del plan, rho, u
+    plan = psn.Plan(512, 12.0, 1e-12, "f32", correction="fourier").build()
+    rho = rho64.to(torch.float32).contiguous()
+    u = torch.empty_like(rho)
+    ms = _timed_solves(torch, plan, rho, u, steps, warmup)
+    out["fourier_correction"] = {"workload": "the n=512 benchmark workload, FP32, correction by the Fourier series",
+                                 "ms": ms, "value": 512.0 ** 3 / (ms * 1e-3)}
+    del plan, rho, u
+    return out
+
+
 def kernel_build_times(psn, torch, n, reps=3):
     """Wall time of psn_kernel_build (setup: mode integrals, correction
     constants, octant assembly, workspace allocation) on the benchmark box."""
@@ -288,6 +333,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-compare", action="store_true", help="skip the FP64 and split paths")
     ap.add_argument("--no-batched", action="store_true", help="skip the mixed-size batched workload")
+    ap.add_argument("--no-options", action="store_true",
+                    help="skip the per-axis grid and Fourier-series correction timings")
     ap.add_argument("--extra-n", type=int, default=256, help="second benchmark size (0 = none)")
     ap.add_argument("--kernel-build", action="store_true",
                     help="only time psn_kernel_build (the setup phase) for the benchmark box, FP32 and FP64, "
@@ -407,6 +454,12 @@ def main():
         log(f"batched: {batched['ms_per_batch']:.3f} ms/batch ({batched['ms_one_by_one']:.3f} ms one by one), "
             f"err {batched['max_rel_err_vs_oracle']}")
 
+    options = None
+    if not args.no_options and n == 512:
+        log("timing the plan options (per-axis grid, Fourier-series correction)")
+        options = bench_options(psn, torch, np, rho64, max(3, args.steps // 4), max(1, args.warmup))
+        log(f"options: {options}")
+
     log("radix-16 DFT: VALU butterflies vs FP32 MFMA")
     r16 = radix16_probe()
     log(f"radix-16: {r16}")
@@ -442,6 +495,7 @@ def main():
         "max_rel_err_vs_oracle": errs or None,
         f"n{args.extra_n}": second,
         "batched": batched,
+        "plan_options": options,
         "radix16_valu_vs_mfma": r16,
     }
     print(json.dumps(line), flush=True)

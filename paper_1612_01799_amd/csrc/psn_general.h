@@ -33,24 +33,31 @@ struct GArgs {
     int n0, n1, n2;
 };
 
-template <int L, class Real>
+// Per step: the axis-2 steps (1, 5) transform the real line as n2/2 packed
+// pairs, a length FL = L/2 transform; the strided steps transform length L.
+// B lines per workgroup: 8 where the lines and the twiddle table fit (the
+// strided steps up to the 160 KB of LDS, so that they move 64-byte FP32 row
+// pieces; the row steps within 64 KB, where more lines only cost occupancy).
+template <int L, class Real, int STEP>
 struct GCfg {
-    static constexpr int E = elems_per_thread(L, sizeof(Real));
-    static constexpr int T = L / E;
+    static constexpr bool rows = STEP == 1 || STEP == 5;
+    static constexpr int FL = rows ? L / 2 : L;
+    static constexpr int E = elems_per_thread(FL, sizeof(Real));
+    static constexpr int T = FL / E;
     static constexpr int CX = sizeof(cx<Real>);
     static constexpr int TWS = TwLds<Real>::slots(L);
     static constexpr int pick() {
         for (int b = 8; b > 1; b /= 2)
-            if ((b * L + TWS) * CX <= 65536 && b * T <= 1024) return b;
+            if ((b * FL + TWS) * CX <= (rows ? 65536 : 163840) && b * T <= 1024) return b;
         return 1;
     }
     static constexpr int B = pick();
-    static constexpr size_t lds = size_t(B * L + TWS) * CX;
+    static constexpr size_t lds = size_t(B * FL + TWS) * CX;
 };
 
 template <int L, class Real, class Io, int STEP>
-__global__ void __launch_bounds__((GCfg<L, Real>::B * GCfg<L, Real>::T)) g_step(const GArgs<Real, Io> a) {
-    using C = GCfg<L, Real>;
+__global__ void __launch_bounds__((GCfg<L, Real, STEP>::B * GCfg<L, Real, STEP>::T)) g_step(const GArgs<Real, Io> a) {
+    using C = GCfg<L, Real, STEP>;
     constexpr int B = C::B, T = C::T;
     constexpr bool rows = STEP == 1 || STEP == 5;
     using Ff = TeamFFT<L, T, Real, -1, false>;
@@ -65,28 +72,54 @@ __global__ void __launch_bounds__((GCfg<L, Real>::B * GCfg<L, Real>::T)) g_step(
     if constexpr (STEP == 1 || STEP == 5) nlines = long(n0) * n1;
     else if constexpr (STEP == 3) nlines = 2L * n1 * h;
     else nlines = long(n0) * h;
-    const long line = long(blockIdx.x) * B + c;
+    // workgroups are dealt to the 8 XCDs round robin: give each XCD a
+    // contiguous run of line groups (neighbours share cache lines in its L2);
+    // the grid is a multiple of 8, and groups past the end leave at once
+    const long grp = long(blockIdx.x % 8) * (gridDim.x / 8) + blockIdx.x / 8;
+    if (grp * B >= nlines) return;  // whole workgroup
+    const long line = grp * B + c;
     const bool live = line < nlines;  // a partial last workgroup still joins every barrier
     const long ln = live ? line : 0;
-    TwLds<Real> tl{sb + B * L};
+    TwLds<Real> tl{sb + B * C::FL};
     tl.fill(a.tw, L, threadIdx.x, B * T);
     __syncthreads();
     LdsCols<Real> lds{sb, B, c};
     cx<Real> d[C::E];
     if constexpr (STEP == 1) {
-        // real row of n2 samples, zero beyond
+        // Real row of n2 = FL samples, zero beyond: z_j = x_2j + i x_2j+1
+        // (j < FL/2, zero beyond), Z = DFT_FL(z), then the padded spectrum
+        // X[k] = E[k] + w^k O[k], w = exp(-2 pi i / L), with E and O the
+        // transforms of the even and odd samples, E = (Z[k] + conj Z[FL-k])/2,
+        // O = (Z[k] - conj Z[FL-k])/(2i); X[0] and X[FL] come from Z[0].
+        constexpr int FL = C::FL;
+        using Fh = TeamFFT<FL, T, Real, -1, false>;
         const Io* x = a.rho + ln * n2;
 #pragma unroll
         for (int e = 0; e < C::E; ++e) {
-            const int p = Ff::in_pos(t, e);
-            d[e] = {(live && p < n2) ? Real(x[p]) : Real(0), Real(0)};
+            const int j = Fh::in_pos(t, e);
+            d[e] = (live && j < FL / 2) ? cx<Real>{Real(x[2 * j]), Real(x[2 * j + 1])} : cx<Real>{Real(0), Real(0)};
         }
-        Ff::run1(d, t, tl, lds);
+        Fh::run1(d, t, TwHalf<Real>{tl}, lds);
+        __syncthreads();  // the transform's last exchange reads are done
+#pragma unroll
+        for (int e = 0; e < C::E; ++e) lds.put(Fh::out_pos(t, e), d[e]);
+        __syncthreads();
         cx<Real>* y = a.w1 + ln * h;
 #pragma unroll
         for (int e = 0; e < C::E; ++e) {
-            const int k = Ff::out_pos(t, e);
-            if (live && k <= n2) gst(y + k, d[e]);
+            const int k = Fh::out_pos(t, e);
+            const cx<Real> Z = lds.get(k);
+            if (k == 0) {
+                if (live) {
+                    gst(y, cx<Real>{Z.x + Z.y, Real(0)});
+                    gst(y + FL, cx<Real>{Z.x - Z.y, Real(0)});
+                }
+            } else {
+                const cx<Real> Zr = conj(lds.get(FL - k));
+                const cx<Real> Ev = scale(Z + Zr, Real(0.5));
+                const cx<Real> Od = rot<-1>(scale(Z - Zr, Real(0.5)));
+                if (live) gst(y + k, Ev + Od * tl(2 * k));
+            }
         }
     } else if constexpr (STEP == 2) {
         const long i0 = ln / h, k2 = ln % h;
@@ -140,30 +173,47 @@ __global__ void __launch_bounds__((GCfg<L, Real>::B * GCfg<L, Real>::T)) g_step(
             if (live && p < n1) gst(y + long(p) * h, d[e]);
         }
     } else {
-        // the row's spectrum is that of a real sequence: X[L - k] = conj X[k]
+        // The row's padded spectrum X[0..FL] is that of a real sequence.  The
+        // inverse of length FL of Y[k] = (X[k] + conj X[FL-k])
+        // + i (X[k] - conj X[FL-k]) w^-k gives z_j = u_2j + i u_2j+1; only
+        // j < FL/2 lies inside the box.
+        constexpr int FL = C::FL;
+        using Fh = TeamFFT<FL, T, Real, +1, false>;
         const cx<Real>* x = a.w1 + ln * h;
 #pragma unroll
         for (int e = 0; e < C::E; ++e) {
-            const int k = Fi::in_pos(t, e);
+            const int k = Fh::in_pos(t, e);
             cx<Real> v{Real(0), Real(0)};
-            if (live) v = k <= n2 ? gld(x + k) : conj(gld(x + (L - k)));
+            if (live) {
+                const cx<Real> p = gld(x + k), q = conj(gld(x + (FL - k)));
+                v = (p + q) + rot<+1>(mul_conj(p - q, tl(2 * k)));
+            }
             d[e] = v;
         }
-        Fi::run1(d, t, tl, lds);
+        Fh::run1(d, t, TwHalf<Real>{tl}, lds);
         Io* y = a.u + ln * n2;
 #pragma unroll
         for (int e = 0; e < C::E; ++e) {
-            const int p = Fi::out_pos(t, e);
-            if (live && p < n2) y[p] = Io(d[e].x);
+            const int j = Fh::out_pos(t, e);
+            if (live && j < FL / 2) {
+                y[2 * j] = Io(d[e].x);
+                y[2 * j + 1] = Io(d[e].y);
+            }
         }
     }
 }
 
 template <int L, class Real, class Io, int STEP>
 hipError_t launch_g_step(const GArgs<Real, Io>& a, long nlines, hipStream_t s) {
-    using C = GCfg<L, Real>;
-    hipLaunchKernelGGL((g_step<L, Real, Io, STEP>), dim3(unsigned((nlines + C::B - 1) / C::B)), dim3(C::B * C::T),
-                       C::lds, s, a);
+    using C = GCfg<L, Real, STEP>;
+    if constexpr (C::lds > 65536) {
+        static const hipError_t ok = hipFuncSetAttribute(reinterpret_cast<const void*>(&g_step<L, Real, Io, STEP>),
+                                                         hipFuncAttributeMaxDynamicSharedMemorySize, int(C::lds));
+        if (ok != hipSuccess) return ok;
+    }
+    const long groups = (nlines + C::B - 1) / C::B;
+    hipLaunchKernelGGL((g_step<L, Real, Io, STEP>), dim3(unsigned(8 * ((groups + 7) / 8))), dim3(C::B * C::T), C::lds,
+                       s, a);
     return hipSuccess;
 }
 
