@@ -120,8 +120,9 @@ psn_status psn_plan_create_box(int n, const double *a, const double *b, double t
  * h_q = (b_q - a_q)/(n_q - 1), per-axis mode tables, delta from
  * min_q (b_q - a_q)/(50 n_q).  Each n_q must be a supported size.  Equal sizes
  * give the same plan as psn_plan_create_box.  Otherwise the plan runs the
- * five steps on plain workspaces (W1 n0 n1 (n2+1), W2 2 n0 n1 (n2+1) complex;
- * split precision stores them in FP64), has no tile schedules
+ * five steps on workspaces with rows of hw = n2 + 1 rounded up to a multiple
+ * of 8 (W1 n0 n1 hw, W2 2 n0 n1 hw complex; split precision stores them in
+ * FP64), has no tile schedules
  * (psn_plan_set_schedule: PSN_EINVAL), takes only the folded correction, and
  * psn_kernel_download fills (n0+1)(n1+1)(n2+1) values.
  * Errors: PSN_EINVAL, PSN_ESIZE, PSN_EFIT. */

@@ -5,16 +5,23 @@
 // of the input formed in registers and only the needed outputs stored:
 //
 //   1  axis 2, real -> complex:  rho[i0][i1][0..n2)  -> W1[i0][i1][0..n2]      (n2 + 1 outputs)
-//   2  axis 1, forward:          W1[i0][0..n1)[k2]   -> W2[i0][0..2n1)[k2]
-//   3  axis 0, forward, x K, inverse, in place on W2[0..n0)[k1][k2]
-//   4  axis 1, inverse:          W2[i0][0..2n1)[k2]  -> W1[i0][0..n1)[k2]
+//   2  axis 1, forward:          W1[i0][0..n1)[k2]   -> W2(i0, 0..2n1, k2)
+//   3  axis 0, forward, x K, inverse, in place on W2(0..n0, k1, k2)
+//   4  axis 1, inverse:          W2(i0, 0..2n1, k2)  -> W1[i0][0..n1)[k2]
 //   5  axis 2, complex -> real:  W1[i0][i1][0..n2]   -> u[i0][i1][0..n2)
 //
-// K is the octant [k0][k1][k2] (k_q = 0..n_q, folded index min(k, 2 n_q - k)),
-// scaled by 1 / (8 n0 n1 n2).  A workgroup holds B lines with the same
-// element stride: consecutive lines of an axis-2 step are rows (threads run
-// along a row), those of the other steps are consecutive k2 (threads of
-// consecutive lines touch consecutive addresses).
+// The workspace rows hold hw = g_pitch(n2) >= n2 + 1 elements (a multiple of
+// kGTile; the tail is never read into a result).  W2 is blocked over k1 as
+// [k1 / KB][i0][k1 % KB][k2] (KB = w2_k1_block(n1), dividing 2 n1): a
+// workgroup of the axis-0 step then spans n0 KB rows instead of the whole
+// array, and one of the axis-1 steps 2 n1 / KB runs of KB rows, so that the
+// pages either touches stay few.  K is the octant
+// (k_q = 0..n_q, folded index min(k, 2 n_q - k)) scaled by 1 / (8 n0 n1 n2),
+// tiled over k2 as g_k_index lays it out.  A workgroup holds B lines with
+// the same element stride: consecutive lines of an axis-2 step are rows
+// (threads run along a row), those of the other steps are consecutive k2 of
+// one aligned tile (threads of consecutive lines touch consecutive
+// addresses; lines with k2 > n2 only pad the tile).
 #pragma once
 
 #include "psn_device.h"
@@ -31,28 +38,47 @@ struct GArgs {
     const Real* K;
     const cx<Real>* tw;  // exp(-2 pi i m / 2L), m < 2L, for this step's length L
     int n0, n1, n2;
+    int kb;  // k1 block of W2
 };
 
-// Per step: the axis-2 steps (1, 5) transform the real line as n2/2 packed
-// pairs, a length FL = L/2 transform; the strided steps transform length L.
-// B lines per workgroup: 8 where the lines and the twiddle table fit (the
-// strided steps up to the 160 KB of LDS, so that they move 64-byte FP32 row
-// pieces; the row steps within 64 KB, where more lines only cost occupancy).
+// Every step runs transforms of length FL = L/2 = n_q.  The axis-2 steps
+// (1, 5) transform the real line as n2/2 packed pairs.  The strided steps split
+// the padded length-L transform of a line whose second half is zero into two
+// length-n_q chains: forward, the even outputs are DFT(x) and the odd ones
+// DFT(x w^p), w = exp(-2 pi i / L); the inverse that keeps the first n_q
+// outputs is IDFT(even) + w^-p IDFT(odd).  The two chains of a line advance in
+// lockstep through one LDS exchange.
+// B lines per workgroup: up to kGTile (a divisor of it), within the 160 KB of
+// LDS for the strided steps (64-byte FP32 row pieces; two workgroups of eight
+// length-512 lines share a CU, which measured faster than one of sixteen) and
+// within 64 KB for the row steps, where more lines only cost occupancy.
+// The row steps keep each line as an LDS row of pitch NP (threads of a team
+// walk along it; the skew of one slot per 16 and a pitch of 8 mod 32 spread a
+// wave's accesses over the banks); the strided steps keep the lines as columns
+// (consecutive lanes, consecutive lines), both chains side by side.  All need
+// the length-FL table exp(-2 pi i m / L), m < 2 FL.  The strided steps take at
+// most 8 elements per thread, so that enough waves fit beside their LDS.
 template <int L, class Real, int STEP>
 struct GCfg {
     static constexpr bool rows = STEP == 1 || STEP == 5;
-    static constexpr int FL = rows ? L / 2 : L;
-    static constexpr int E = elems_per_thread(FL, sizeof(Real));
+    static constexpr int FL = L / 2;
+    static constexpr int E = elems_per_thread(FL, rows ? int(sizeof(Real)) : 8);
     static constexpr int T = FL / E;
     static constexpr int CX = sizeof(cx<Real>);
-    static constexpr int TWS = TwLds<Real>::slots(L);
+    static constexpr int TWS = TwLds<Real>::slots(FL);
+    static constexpr int pitch() {
+        int np = FL + (FL >> 4) + 1;
+        while (np % 32 != 8) ++np;
+        return np;
+    }
+    static constexpr int NP = rows ? pitch() : 2 * FL;  // LDS elements per line
     static constexpr int pick() {
-        for (int b = 8; b > 1; b /= 2)
-            if ((b * FL + TWS) * CX <= (rows ? 65536 : 163840) && b * T <= 1024) return b;
+        for (int b = psn_host::kGTile; b > 1; b /= 2)
+            if ((b * NP + TWS) * CX <= (rows ? 65536 : 163840) && b * T <= 1024) return b;
         return 1;
     }
     static constexpr int B = pick();
-    static constexpr size_t lds = size_t(B * FL + TWS) * CX;
+    static constexpr size_t lds = size_t(B * NP + TWS) * CX;
 };
 
 template <int L, class Real, class Io, int STEP>
@@ -60,38 +86,50 @@ __global__ void __launch_bounds__((GCfg<L, Real, STEP>::B * GCfg<L, Real, STEP>:
     using C = GCfg<L, Real, STEP>;
     constexpr int B = C::B, T = C::T;
     constexpr bool rows = STEP == 1 || STEP == 5;
-    using Ff = TeamFFT<L, T, Real, -1, false>;
-    using Fi = TeamFFT<L, T, Real, +1, STEP == 3>;
+    constexpr int FL = C::FL;
+    using Ff = TeamFFT<FL, T, Real, -1, false>;
+    using Fi = TeamFFT<FL, T, Real, +1, STEP == 3>;
     extern __shared__ __align__(16) unsigned char smem[];
     cx<Real>* sb = reinterpret_cast<cx<Real>*>(smem);
     const int n0 = a.n0, n1 = a.n1, n2 = a.n2;
-    const int h = n2 + 1;  // k2 per row of the workspaces
+    const int h = n2 + 1;                 // k2 of the spectrum
+    const long hw = psn_host::g_pitch(n2);  // elements per workspace row
+    const int kb = a.kb;
+    // offset of W2 row (i0, k1)
+    auto w2row = [&](long i0, long k1) { return ((k1 / kb) * n0 + i0) * kb * hw + (k1 % kb) * hw; };
     const int c = rows ? int(threadIdx.x) / T : int(threadIdx.x) % B;
     const int t = rows ? int(threadIdx.x) % T : int(threadIdx.x) / B;
     long nlines;
     if constexpr (STEP == 1 || STEP == 5) nlines = long(n0) * n1;
-    else if constexpr (STEP == 3) nlines = 2L * n1 * h;
-    else nlines = long(n0) * h;
+    else if constexpr (STEP == 3) nlines = 2L * n1 * hw;
+    else nlines = long(n0) * hw;
     // workgroups are dealt to the 8 XCDs round robin: give each XCD a
     // contiguous run of line groups (neighbours share cache lines in its L2);
     // the grid is a multiple of 8, and groups past the end leave at once
     const long grp = long(blockIdx.x % 8) * (gridDim.x / 8) + blockIdx.x / 8;
     if (grp * B >= nlines) return;  // whole workgroup
     const long line = grp * B + c;
-    const bool live = line < nlines;  // a partial last workgroup still joins every barrier
+    // a partial last workgroup, and the lines of a tile past k2 = n2, still
+    // join every barrier
+    const bool live = line < nlines && (rows || line % hw < h);
     const long ln = live ? line : 0;
-    TwLds<Real> tl{sb + B * C::FL};
-    tl.fill(a.tw, L, threadIdx.x, B * T);
+    // the length-FL table from every other entry of the step's length-L table
+    TwLds<Real> tl{sb + B * C::NP};
+    for (int i = threadIdx.x; i < L; i += B * T) tl.p[TwLds<Real>::at(i)] = a.tw[2 * i];
     __syncthreads();
-    LdsCols<Real> lds{sb, B, c};
-    cx<Real> d[C::E];
+    using View = std::conditional_t<rows, LdsRows<Real>, LdsCols2<Real>>;
+    View lds = [&] {
+        if constexpr (rows) return LdsRows<Real>{sb + c * C::NP};
+        else return LdsCols2<Real>{sb, B, c};
+    }();
+    cx<Real> d[C::E];          // the row steps' line
+    cx<Real> d2[2][C::E];      // the strided steps' two chains
     if constexpr (STEP == 1) {
         // Real row of n2 = FL samples, zero beyond: z_j = x_2j + i x_2j+1
         // (j < FL/2, zero beyond), Z = DFT_FL(z), then the padded spectrum
         // X[k] = E[k] + w^k O[k], w = exp(-2 pi i / L), with E and O the
         // transforms of the even and odd samples, E = (Z[k] + conj Z[FL-k])/2,
         // O = (Z[k] - conj Z[FL-k])/(2i); X[0] and X[FL] come from Z[0].
-        constexpr int FL = C::FL;
         using Fh = TeamFFT<FL, T, Real, -1, false>;
         const Io* x = a.rho + ln * n2;
 #pragma unroll
@@ -99,12 +137,12 @@ __global__ void __launch_bounds__((GCfg<L, Real, STEP>::B * GCfg<L, Real, STEP>:
             const int j = Fh::in_pos(t, e);
             d[e] = (live && j < FL / 2) ? cx<Real>{Real(x[2 * j]), Real(x[2 * j + 1])} : cx<Real>{Real(0), Real(0)};
         }
-        Fh::run1(d, t, TwHalf<Real>{tl}, lds);
+        Fh::run1(d, t, tl, lds);
         __syncthreads();  // the transform's last exchange reads are done
 #pragma unroll
         for (int e = 0; e < C::E; ++e) lds.put(Fh::out_pos(t, e), d[e]);
         __syncthreads();
-        cx<Real>* y = a.w1 + ln * h;
+        cx<Real>* y = a.w1 + ln * hw;
 #pragma unroll
         for (int e = 0; e < C::E; ++e) {
             const int k = Fh::out_pos(t, e);
@@ -118,79 +156,92 @@ __global__ void __launch_bounds__((GCfg<L, Real, STEP>::B * GCfg<L, Real, STEP>:
                 const cx<Real> Zr = conj(lds.get(FL - k));
                 const cx<Real> Ev = scale(Z + Zr, Real(0.5));
                 const cx<Real> Od = rot<-1>(scale(Z - Zr, Real(0.5)));
-                if (live) gst(y + k, Ev + Od * tl(2 * k));
+                if (live) gst(y + k, Ev + Od * tl(k));
             }
         }
     } else if constexpr (STEP == 2) {
-        const long i0 = ln / h, k2 = ln % h;
-        const cx<Real>* x = a.w1 + i0 * n1 * h + k2;
+        const long i0 = ln / hw, k2 = ln % hw;
+        const cx<Real>* x = a.w1 + i0 * n1 * hw + k2;
 #pragma unroll
         for (int e = 0; e < C::E; ++e) {
             const int p = Ff::in_pos(t, e);
-            d[e] = (live && p < n1) ? gld(x + long(p) * h) : cx<Real>{Real(0), Real(0)};
+            d2[0][e] = live ? gld(x + long(p) * hw) : cx<Real>{Real(0), Real(0)};
+            d2[1][e] = d2[0][e] * a.tw[2 * p];
         }
-        Ff::run1(d, t, tl, lds);
-        cx<Real>* y = a.w2 + i0 * 2 * n1 * h + k2;
+        Ff::template run<2>(d2, t, tl, lds);
+        cx<Real>* y = a.w2 + k2;  // output k1 = 2m + chain
 #pragma unroll
         for (int e = 0; e < C::E; ++e)
-            if (live) gst(y + long(Ff::out_pos(t, e)) * h, d[e]);
+            if (live) {
+                const long m = Ff::out_pos(t, e);
+                gst(y + w2row(i0, 2 * m), d2[0][e]);
+                gst(y + w2row(i0, 2 * m + 1), d2[1][e]);
+            }
     } else if constexpr (STEP == 3) {
-        const long k1 = ln / h, k2 = ln % h;
-        const long s0 = 2L * n1 * h;
-        cx<Real>* x = a.w2 + ln;
+        const long k1 = ln / hw, k2 = ln % hw;
+        const long s0 = long(kb) * hw;  // i0 stride
+        cx<Real>* x = a.w2 + w2row(0, k1) + k2;
+        cx<Real> w[C::E];  // w^p of each input position
 #pragma unroll
         for (int e = 0; e < C::E; ++e) {
             const int p = Ff::in_pos(t, e);
-            d[e] = (live && p < n0) ? gld(x + long(p) * s0) : cx<Real>{Real(0), Real(0)};
+            w[e] = a.tw[2 * p];
+            d2[0][e] = live ? gld(x + long(p) * s0) : cx<Real>{Real(0), Real(0)};
+            d2[1][e] = d2[0][e] * w[e];
         }
-        Ff::run1(d, t, tl, lds);
-        const long k1f = k1 <= n1 ? k1 : 2 * n1 - k1;
-        const Real* Kr = a.K + k1f * h + k2;
-        const long sk0 = long(n1 + 1) * h;
+        Ff::template run<2>(d2, t, tl, lds);
+        // kernel values of outputs k0 = 2m + chain at the folded index
+        const int k1f = int(k1 <= n1 ? k1 : 2 * n1 - k1);
+        const Real* Kr = a.K + psn_host::g_k_index(n0, n2, 0, k1f, int(k2));  // k0 steps by kGTile
+        Real kk[2][C::E];
 #pragma unroll
-        for (int e = 0; e < C::E; ++e) {
-            const int k0 = Ff::out_pos(t, e);
-            const int k0f = k0 <= n0 ? k0 : 2 * n0 - k0;
-            d[e] = scale(d[e], live ? Real(Kr[k0f * sk0]) : Real(0));
-        }
-        __syncthreads();  // the forward transform's last exchange reads are done
-        Fi::run1(d, t, tl, lds);  // radices reversed: starts from the forward output layout
+        for (int e = 0; e < C::E; ++e)
 #pragma unroll
-        for (int e = 0; e < C::E; ++e) {
-            const int p = Fi::out_pos(t, e);
-            if (live && p < n0) gst(x + long(p) * s0, d[e]);
-        }
+            for (int ch = 0; ch < 2; ++ch) {
+                const int k0 = 2 * Ff::out_pos(t, e) + ch;
+                const int k0f = k0 <= n0 ? k0 : 2 * n0 - k0;
+                kk[ch][e] = live ? Real(Kr[k0f * psn_host::kGTile]) : Real(0);
+            }
+        // radices reversed: starts from the forward output layout and ends in
+        // its input layout (slot e at position Ff::in_pos(t, e))
+        Fi::template run_scaled<2>(d2, t, tl, lds, kk);
+#pragma unroll
+        for (int e = 0; e < C::E; ++e)
+            if (live) gst(x + long(Ff::in_pos(t, e)) * s0, twfma<+1>(d2[1][e], w[e], d2[0][e]));
     } else if constexpr (STEP == 4) {
-        const long i0 = ln / h, k2 = ln % h;
-        const cx<Real>* x = a.w2 + i0 * 2 * n1 * h + k2;
+        const long i0 = ln / hw, k2 = ln % hw;
+        const cx<Real>* x = a.w2 + k2;  // input k1 = 2m + chain
 #pragma unroll
-        for (int e = 0; e < C::E; ++e) d[e] = live ? gld(x + long(Fi::in_pos(t, e)) * h) : cx<Real>{Real(0), Real(0)};
-        Fi::run1(d, t, tl, lds);
-        cx<Real>* y = a.w1 + i0 * n1 * h + k2;
+        for (int e = 0; e < C::E; ++e) {
+            const long m = Fi::in_pos(t, e);
+            d2[0][e] = live ? gld(x + w2row(i0, 2 * m)) : cx<Real>{Real(0), Real(0)};
+            d2[1][e] = live ? gld(x + w2row(i0, 2 * m + 1)) : cx<Real>{Real(0), Real(0)};
+        }
+        Fi::template run<2>(d2, t, tl, lds);
+        cx<Real>* y = a.w1 + i0 * n1 * hw + k2;
 #pragma unroll
         for (int e = 0; e < C::E; ++e) {
             const int p = Fi::out_pos(t, e);
-            if (live && p < n1) gst(y + long(p) * h, d[e]);
+            if (live) gst(y + long(p) * hw, twfma<+1>(d2[1][e], a.tw[2 * p], d2[0][e]));
         }
     } else {
         // The row's padded spectrum X[0..FL] is that of a real sequence.  The
         // inverse of length FL of Y[k] = (X[k] + conj X[FL-k])
         // + i (X[k] - conj X[FL-k]) w^-k gives z_j = u_2j + i u_2j+1; only
         // j < FL/2 lies inside the box.
-        constexpr int FL = C::FL;
         using Fh = TeamFFT<FL, T, Real, +1, false>;
-        const cx<Real>* x = a.w1 + ln * h;
+        const cx<Real>* x = a.w1 + ln * hw;
 #pragma unroll
         for (int e = 0; e < C::E; ++e) {
             const int k = Fh::in_pos(t, e);
             cx<Real> v{Real(0), Real(0)};
             if (live) {
                 const cx<Real> p = gld(x + k), q = conj(gld(x + (FL - k)));
-                v = (p + q) + rot<+1>(mul_conj(p - q, tl(2 * k)));
+                v = (p + q) + rot<+1>(mul_conj(p - q, tl(k)));
             }
             d[e] = v;
         }
-        Fh::run1(d, t, TwHalf<Real>{tl}, lds);
+        Fh::run1(d, t, tl, lds);
         Io* y = a.u + ln * n2;
 #pragma unroll
         for (int e = 0; e < C::E; ++e) {

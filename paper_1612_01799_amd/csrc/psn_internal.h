@@ -38,8 +38,8 @@ struct psn_plan {
     bool tuned = false;
     // near-zone correction: folded into K, or added by its Fourier series
     int correction = PSN_CORRECTION_FOLDED;
-    // points per axis; `general` when they differ (the five-step path with
-    // plain workspaces and a plain [k0][k1][k2] octant)
+    // points per axis; `general` when they differ (the five-step path, with
+    // the workspace and octant layouts of g_pitch and g_k_index)
     int ng[3] = {0, 0, 0};
     bool general = false;
 };
@@ -58,6 +58,18 @@ __host__ __device__ constexpr int k_tile(int n) { return n % 8 == 0 ? 8 : n % 4 
 __host__ __device__ constexpr size_t k_index(int n, int kt1, int kt0, int k2) {
     return (size_t(kt1) * (n / k_tile(n)) + k2 / k_tile(n)) * size_t(n + 1) * k_tile(n) + size_t(kt0) * k_tile(n) +
            k2 % k_tile(n);
+}
+
+// Grids with per-axis sizes: the k2 extent n2 + 1 of the workspaces' rows and
+// of the kernel octant is padded to a multiple of kGTile, so that a workgroup
+// of the strided steps (up to kGTile consecutive k2) moves whole aligned row
+// pieces; the octant is tiled over k2 as [k1][k2 / kGTile][k0][k2 % kGTile],
+// so that the axis-0 step's workgroup (one k1, one tile) reads one run.
+constexpr int kGTile = 8;
+__host__ __device__ constexpr long g_pitch(int n2) { return (long(n2) + kGTile) / kGTile * kGTile; }
+__host__ __device__ constexpr size_t g_k_index(int n0, int n2, int k0, int k1, int k2) {
+    return ((size_t(k1) * size_t(g_pitch(n2) / kGTile) + size_t(k2 / kGTile)) * size_t(n0 + 1) + size_t(k0)) * kGTile +
+           size_t(k2 % kGTile);
 }
 
 // k1 block of the W2 layout: the largest power of two <= sqrt(2n) dividing 2n

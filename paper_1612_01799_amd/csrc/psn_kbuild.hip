@@ -308,8 +308,8 @@ __global__ void __launch_bounds__(256) k_gemm(const double* __restrict__ A0, con
     }
 }
 
-// Octant of a grid with per-axis sizes, plain layout [k0][k1][k2] with
-// k_q = 0..n_q: one thread per k2, sum over the terms.  A_q has rows of n_q + 1.
+// Octant of a grid with per-axis sizes, k_q = 0..n_q, in the k2-tiled layout
+// of g_k_index: one thread per k2, sum over the terms.  A_q has rows of n_q + 1.
 template <class Kt>
 __global__ void g_assemble(const double* __restrict__ A0, const double* __restrict__ A1,
                            const double* __restrict__ A2, const double* __restrict__ w, int terms, int n0, int n1,
@@ -323,7 +323,7 @@ __global__ void g_assemble(const double* __restrict__ A0, const double* __restri
                 s);
     const double b0 = 2.0 * kPi * k0 / p0, b1 = 2.0 * kPi * k1 / p1, b2 = 2.0 * kPi * k2 / p2;
     const double v = s + fold * (Cc[0] - (Cc[1] / 6.0) * (b0 * b0 + b1 * b1 + b2 * b2));
-    K[(size_t(k0) * (n1 + 1) + k1) * (n2 + 1) + k2] = Kt(scale * v);
+    K[psn_host::g_k_index(n0, n2, k0, k1, k2)] = Kt(scale * v);
 }
 
 }  // namespace psn

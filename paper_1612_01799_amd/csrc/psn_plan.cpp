@@ -246,8 +246,9 @@ double algorithmic_bytes(const psn_plan* p) {
     return 2 * bio * n3 + 4 * b1 * n3 + 8 * b2 * n3 + bk * np1 * np1 * np1;
 }
 
-// complex workspace elements of a grid with per-axis sizes
-size_t general_w1(const psn_plan* p) { return size_t(p->ng[0]) * p->ng[1] * (p->ng[2] + 1); }
+// complex workspace elements of a grid with per-axis sizes (rows padded to
+// g_pitch(n2) >= n2 + 1 elements)
+size_t general_w1(const psn_plan* p) { return size_t(p->ng[0]) * p->ng[1] * psn_host::g_pitch(p->ng[2]); }
 size_t general_w2(const psn_plan* p) { return 2 * general_w1(p); }
 size_t general_cx(const psn_plan* p) { return p->dtype == PSN_F32 ? 8 : 16; }
 
@@ -459,9 +460,10 @@ psn_status psn_kernel_build(psn_plan* p, void* stream) {
     psn_status st = PSN_OK;
     const size_t cxb = p->dtype == PSN_F32 ? 8 : 16;
     if (p->general) {
-        // plain octant, per-axis twiddle tables of 4 n_q entries, plain workspaces
+        // octant tiled over k2, per-axis twiddle tables of 4 n_q entries,
+        // workspaces with padded rows
         const size_t g0 = p->ng[0], g1 = p->ng[1], g2 = p->ng[2];
-        if ((st = dev_alloc(&p->K, (g0 + 1) * (g1 + 1) * (g2 + 1) * kb, &tot)) ||
+        if ((st = dev_alloc(&p->K, (g0 + 1) * (g1 + 1) * size_t(psn_host::g_pitch(p->ng[2])) * kb, &tot)) ||
             (st = dev_alloc(&p->Kb, kb, &tot)) || (st = dev_alloc(&p->tw, 4 * (g0 + g1 + g2) * cxb, &tot)) ||
             (st = dev_alloc(&p->W1, general_w1(p) * general_cx(p), &tot)) ||
             (st = dev_alloc(&p->W2, general_w2(p) * general_cx(p), &tot))) {
@@ -891,15 +893,19 @@ psn_status psn_kernel_download(const psn_plan* p, double* octant) {
     if (!p || !octant) return PSN_EINVAL;
     if (!p->built) return PSN_ESTATE;
     if (p->general) {
-        const size_t g0 = p->ng[0], g1 = p->ng[1], g2 = p->ng[2];
-        const size_t cnt = (g0 + 1) * (g1 + 1) * (g2 + 1);
+        const int g0 = p->ng[0], g1 = p->ng[1], g2 = p->ng[2];
         const size_t kb = psn_host::kernel_elem_bytes(p->dtype);
-        std::vector<unsigned char> hk(cnt * kb);
+        std::vector<unsigned char> hk(size_t(g0 + 1) * (g1 + 1) * size_t(psn_host::g_pitch(g2)) * kb);
         if (!hip_ok(hipMemcpy(hk.data(), p->K, hk.size(), hipMemcpyDeviceToHost), "copy K")) return PSN_EDEVICE;
         const double inv = 8.0 * double(g0) * g1 * g2;
-        for (size_t i = 0; i < cnt; ++i)
-            octant[i] = (kb == 4 ? (double)reinterpret_cast<const float*>(hk.data())[i]
-                                 : reinterpret_cast<const double*>(hk.data())[i]) * inv;
+        size_t i = 0;  // plain [k0][k1][k2] order
+        for (int k0 = 0; k0 <= g0; ++k0)
+            for (int k1 = 0; k1 <= g1; ++k1)
+                for (int k2 = 0; k2 <= g2; ++k2, ++i) {
+                    const size_t j = psn_host::g_k_index(g0, g2, k0, k1, k2);
+                    octant[i] = (kb == 4 ? (double)reinterpret_cast<const float*>(hk.data())[j]
+                                         : reinterpret_cast<const double*>(hk.data())[j]) * inv;
+                }
         return PSN_OK;
     }
     const size_t n = p->n, np1 = n + 1;
