@@ -78,6 +78,7 @@ struct GCfg {
         return 1;
     }
     static constexpr int B = pick();
+    static_assert(psn_host::kGTile % B == 0, "a strided workgroup lies inside one k2 tile");
     static constexpr size_t lds = size_t(B * NP + TWS) * CX;
 };
 
@@ -111,8 +112,8 @@ __global__ void __launch_bounds__((GCfg<L, Real, STEP>::B * GCfg<L, Real, STEP>:
     const long line = grp * B + c;
     // a partial last workgroup, and the lines of a tile past k2 = n2, still
     // join every barrier
-    const bool live = line < nlines && (rows || line % hw < h);
-    const long ln = live ? line : 0;
+    [[maybe_unused]] const bool live = line < nlines && (rows || line % hw < h);
+    [[maybe_unused]] const long ln = live ? line : 0;
     // the length-FL table from every other entry of the step's length-L table
     TwLds<Real> tl{sb + B * C::NP};
     for (int i = threadIdx.x; i < L; i += B * T) tl.p[TwLds<Real>::at(i)] = a.tw[2 * i];
@@ -178,36 +179,57 @@ __global__ void __launch_bounds__((GCfg<L, Real, STEP>::B * GCfg<L, Real, STEP>:
                 gst(y + w2row(i0, 2 * m + 1), d2[1][e]);
             }
     } else if constexpr (STEP == 3) {
-        const long k1 = ln / hw, k2 = ln % hw;
-        const long s0 = long(kb) * hw;  // i0 stride
-        cx<Real>* x = a.w2 + w2row(0, k1) + k2;
-        cx<Real> w[C::E];  // w^p of each input position
+        // B divides hw, and 2 n1 hw lines are whole workgroups: a workgroup
+        // holds one k1 and one aligned k2 tile, every lane addresses W2 and K
+        // inside their rows (lanes past k2 = n2 work on the padding), and the
+        // addresses are a workgroup-uniform base per element plus one 32-bit
+        // lane offset.  The axis length n0 is the compile-time FL.
+        constexpr int N0 = FL;
+        const long line0 = grp * B;
+        const long k1 = line0 / hw, k2b = line0 % hw;
+        const uint32_t s0 = uint32_t(kb) * uint32_t(hw);  // i0 stride
+        cx<Real>* const xu = a.w2 + w2row(0, k1) + k2b;
+        const uint32_t xl = (uint32_t(c) + uint32_t(t) * s0) * uint32_t(sizeof(cx<Real>));
+        const uint32_t wl = uint32_t(2 * t) * uint32_t(sizeof(cx<Real>));
+        cx<Real> w[C::E];  // w^p of each input position p = t + in_pos(0, e)
 #pragma unroll
         for (int e = 0; e < C::E; ++e) {
-            const int p = Ff::in_pos(t, e);
-            w[e] = a.tw[2 * p];
-            d2[0][e] = live ? gld(x + long(p) * s0) : cx<Real>{Real(0), Real(0)};
+            const int p0 = Ff::in_pos(0, e);
+            w[e] = gld(byte_off(sbase(a.tw + 2 * p0), wl));
+            d2[0][e] = gld(byte_off(sbase(xu + size_t(p0) * s0), xl));
             d2[1][e] = d2[0][e] * w[e];
         }
         Ff::template run<2>(d2, t, tl, lds);
-        // kernel values of outputs k0 = 2m + chain at the folded index
+        // kernel values of the outputs k0 = 2m + chain, m = t + out_pos(0, e),
+        // at the folded index min(k0, 2 n0 - k0); the folded k0 steps by
+        // kGTile.  An element whose k0 all lie on one side of n0 is a uniform
+        // base plus the lane offset 2t or -2t (written as 2 (T - 1 - t)).
+        constexpr int KT = psn_host::kGTile;
         const int k1f = int(k1 <= n1 ? k1 : 2 * n1 - k1);
-        const Real* Kr = a.K + psn_host::g_k_index(n0, n2, 0, k1f, int(k2));  // k0 steps by kGTile
+        const Real* const Ku = a.K + psn_host::g_k_index(N0, n2, 0, k1f, int(k2b));
+        const uint32_t kup = (uint32_t(2 * KT) * uint32_t(t) + uint32_t(c)) * uint32_t(sizeof(Real));
+        const uint32_t kdn = (uint32_t(2 * KT) * uint32_t(T - 1 - t) + uint32_t(c)) * uint32_t(sizeof(Real));
         Real kk[2][C::E];
 #pragma unroll
         for (int e = 0; e < C::E; ++e)
 #pragma unroll
             for (int ch = 0; ch < 2; ++ch) {
-                const int k0 = 2 * Ff::out_pos(t, e) + ch;
-                const int k0f = k0 <= n0 ? k0 : 2 * n0 - k0;
-                kk[ch][e] = live ? Real(Kr[k0f * psn_host::kGTile]) : Real(0);
+                const int a0 = 2 * Ff::out_pos(0, e) + ch;  // k0 of lane t = 0
+                if (a0 + 2 * (T - 1) <= N0) {
+                    kk[ch][e] = gld(byte_off(sbase(Ku + a0 * KT), kup));
+                } else if (a0 >= N0) {
+                    kk[ch][e] = gld(byte_off(sbase(Ku + (2 * N0 - a0 - 2 * (T - 1)) * KT), kdn));
+                } else {
+                    const int k0 = a0 + 2 * t;
+                    kk[ch][e] = Ku[(k0 <= N0 ? k0 : 2 * N0 - k0) * KT + c];
+                }
             }
         // radices reversed: starts from the forward output layout and ends in
         // its input layout (slot e at position Ff::in_pos(t, e))
         Fi::template run_scaled<2>(d2, t, tl, lds, kk);
 #pragma unroll
         for (int e = 0; e < C::E; ++e)
-            if (live) gst(x + long(Ff::in_pos(t, e)) * s0, twfma<+1>(d2[1][e], w[e], d2[0][e]));
+            gst(byte_off(sbase(xu + size_t(Ff::in_pos(0, e)) * s0), xl), twfma<+1>(d2[1][e], w[e], d2[0][e]));
     } else if constexpr (STEP == 4) {
         const long i0 = ln / hw, k2 = ln % hw;
         const cx<Real>* x = a.w2 + k2;  // input k1 = 2m + chain

@@ -309,14 +309,19 @@ __global__ void __launch_bounds__(256) k_gemm(const double* __restrict__ A0, con
 }
 
 // Octant of a grid with per-axis sizes, k_q = 0..n_q, in the k2-tiled layout
-// of g_k_index: one thread per k2, sum over the terms.  A_q has rows of n_q + 1.
+// of g_k_index: one thread per k2, sum over the terms; the padding k2 > n2 of
+// the last tile is set to zero.  A_q has rows of n_q + 1.
 template <class Kt>
 __global__ void g_assemble(const double* __restrict__ A0, const double* __restrict__ A1,
                            const double* __restrict__ A2, const double* __restrict__ w, int terms, int n0, int n1,
                            int n2, double p0, double p1, double p2, const double* __restrict__ Cc, double fold,
                            double scale, Kt* __restrict__ K) {
     const int k2 = blockIdx.x * blockDim.x + threadIdx.x, k1 = blockIdx.y, k0 = blockIdx.z;
-    if (k2 > n2) return;
+    if (k2 >= psn_host::g_pitch(n2)) return;
+    if (k2 > n2) {
+        K[psn_host::g_k_index(n0, n2, k0, k1, k2)] = Kt(0);
+        return;
+    }
     double s = 0.0;
     for (int j = 0; j < terms; ++j)
         s = fma(A0[size_t(j) * (n0 + 1) + k0] * A1[size_t(j) * (n1 + 1) + k1], w[j] * A2[size_t(j) * (n2 + 1) + k2],
@@ -378,7 +383,7 @@ hipError_t launch_kernel_build(psn_plan* p, const double* d_tau, const double* d
     if (p->general) {
         const int n0 = p->ng[0], n1 = p->ng[1], n2 = p->ng[2];
         const double scale = 1.0 / (8.0 * double(n0) * n1 * n2);
-        const dim3 g((n2 + 1 + 127) / 128, n1 + 1, n0 + 1);
+        const dim3 g(unsigned((psn_host::g_pitch(n2) + 127) / 128), n1 + 1, n0 + 1);
         if (p->dtype == PSN_F32)
             hipLaunchKernelGGL(psn::g_assemble<float>, g, dim3(128), 0, s, A[0], A[1], A[2], d_w, terms, n0, n1, n2,
                                p->period[0], p->period[1], p->period[2], d_c, 1.0, scale, static_cast<float*>(p->K));
