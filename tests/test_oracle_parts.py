@@ -32,6 +32,27 @@ def test_delta_floor():
     assert g.delta == pytest.approx(1e-3, rel=1e-15)
 
 
+@pytest.mark.parametrize("a,b,n", [((-300.0,) * 3, (300.0,) * 3, (16,) * 3),
+                                   ((-1.0, -7.0, -2.0), (3.0, 5.0, 2.5), (16, 96, 24)),
+                                   ((-40.0, -10.0, -10.0), (40.0, 10.0, 10.0), (8, 16, 16)),
+                                   ((-12.0,) * 3, (12.0,) * 3, (512,) * 3)])
+def test_delta_lies_in_the_papers_interval(a, b, n):
+    """Section 2 asks for delta in (0, min_q (b_q - a_q) / (2 lambda)) in the
+    standardised frame x = lambda x' + c, and section 3 says its heuristic
+    lies there whenever lambda <= 25 min_q n_q.  So the near-zone ball, of
+    physical radius lambda * delta, lies inside the box's shortest half-edge.
+    A reading that scaled the heuristic by lambda once more leaves the
+    interval on the first and third boxes (0.75 -> 225 against 1, and
+    0.025 -> 1 against 0.25)."""
+    box = W.Box(a, b, n)
+    g = O.geometry(box)
+    lam = max(0.5 * (b[q] - a[q]) for q in range(3))
+    assert lam <= 25 * min(n)
+    d_std = g.delta / lam
+    assert 1e-3 <= d_std < min((b[q] - a[q]) / (2 * lam) for q in range(3))
+    assert g.delta < min(0.5 * (b[q] - a[q]) for q in range(3))
+
+
 # ------------------------------------------------------------------ Gaussian sum
 @pytest.mark.parametrize("L,n,eps", [(6.0, 32, 1e-12), (8.0, 128, 1e-12), (12.0, 512, 1e-12),
                                      (2.0, 16, 1e-8), (10.0, 256, 1e-14)])
