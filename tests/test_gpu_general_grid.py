@@ -84,3 +84,40 @@ def test_equal_sizes_give_the_cube_plan():
     q = psn.Plan(32, 2.0, 1e-12, "f32").build()
     assert p.info()["schedule"] == q.info()["schedule"]
     assert np.array_equal(p.kernel_octant(), q.kernel_octant())
+
+
+_BENCH_GRID = {}
+
+
+def _bench_grid():
+    """The per-axis workload the benchmark times: 512 x 512 x 384 points at the
+    spacing h = 24/511 of the n = 512 cube, a 64-Gaussian mixture (seed 1006),
+    and the oracle's FP64 solution on it (about 20 s of host time)."""
+    if not _BENCH_GRID:
+        n3, h = (512, 512, 384), 24.0 / 511
+        a = tuple(-0.5 * h * (q - 1) for q in n3)
+        b = tuple(0.5 * h * (q - 1) for q in n3)
+        box = W.Box(a, b, n3)
+        mix = W.draw_mixture(1006, 64, -0.5 * min(b), 0.5 * min(b), 0.3, 2.0, 0.5, 1.5, box)
+        rho = W.mixture_density(mix)
+        ks = O.kernel_spectrum(box, 1e-12)
+        _BENCH_GRID.update(n3=n3, a=a, b=b, rho=rho, octant=ks.octant, ref=O.solve(rho, O.half_spectrum(ks)))
+    return _BENCH_GRID
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f64", "split"])
+def test_general_grid_at_benchmark_size_matches_oracle(dtype):
+    """Every point of the benchmark's per-axis grid in the launch configuration
+    the benchmark times (padded rows, k1-blocked W2, k2-tiled octant at full
+    size, where 32-bit lane offsets are largest)."""
+    torch = torch_cuda()
+    g = _bench_grid()
+    plan = psn.Plan(g["n3"], box=(g["a"], g["b"]), tol=1e-12, dtype=dtype).build()
+    u = plan.solve(torch.from_numpy(g["rho"]).to("cuda", plan.io_dtype()))
+    torch.cuda.synchronize()
+    err = max_rel(u.double().cpu().numpy(), g["ref"])
+    print(f"grid {g['n3']} {dtype}: {err:.3e}", flush=True)
+    assert err <= TOL[dtype]
+    if dtype == "f64":
+        K = plan.kernel_octant()
+        assert np.max(np.abs(K - g["octant"])) <= 1e-13 * abs(g["octant"][0, 0, 0])
