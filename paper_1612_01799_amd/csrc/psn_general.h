@@ -11,11 +11,13 @@
 //   5  axis 2, complex -> real:  W1[i0][i1][0..n2]   -> u[i0][i1][0..n2)
 //
 // The workspace rows hold hw = g_pitch(n2) >= n2 + 1 elements (a multiple of
-// kGTile; the tail is never read into a result).  W2 is blocked over k1 as
-// [k1 / KB][i0][k1 % KB][k2] (KB = w2_k1_block(n1), dividing 2 n1): a
-// workgroup of the axis-0 step then spans n0 KB rows instead of the whole
-// array, and one of the axis-1 steps 2 n1 / KB runs of KB rows, so that the
-// pages either touches stay few.  K is the octant
+// kGTile; the tail is never read into a result).  W2 is blocked over k1 and
+// tiled over k2 as [k1 / KB][i0][k2 / kGTile][k1 % KB][k2 % kGTile]
+// (KB = w2_k1_block(n1), dividing 2 n1): a workgroup of the axis-0 step then
+// spans n0 KB rows instead of the whole array, and one of the axis-1 steps
+// 2 n1 / KB runs of KB kGTile elements, consecutive k1 of its tile next to
+// each other, so that its two chains' stores fill whole lines and the pages
+// either step touches stay few.  K is the octant
 // (k_q = 0..n_q, folded index min(k, 2 n_q - k)) scaled by 1 / (8 n0 n1 n2),
 // tiled over k2 as g_k_index lays it out.  A workgroup holds B lines with
 // the same element stride: consecutive lines of an axis-2 step are rows
@@ -97,7 +99,11 @@ __global__ void __launch_bounds__((GCfg<L, Real, STEP>::B * GCfg<L, Real, STEP>:
     const long hw = psn_host::g_pitch(n2);  // elements per workspace row
     const int kb = a.kb;
     // offset of W2 row (i0, k1)
-    auto w2row = [&](long i0, long k1) { return ((k1 / kb) * n0 + i0) * kb * hw + (k1 % kb) * hw; };
+    // offset of W2 element (i0, k1, k2)
+    constexpr long KT = psn_host::kGTile;
+    auto w2at = [&](long i0, long k1, long k2) {
+        return (((k1 / kb) * n0 + i0) * (hw / KT) + k2 / KT) * (kb * KT) + (k1 % kb) * KT + k2 % KT;
+    };
     const int c = rows ? int(threadIdx.x) / T : int(threadIdx.x) % B;
     const int t = rows ? int(threadIdx.x) % T : int(threadIdx.x) / B;
     long nlines;
@@ -170,25 +176,32 @@ __global__ void __launch_bounds__((GCfg<L, Real, STEP>::B * GCfg<L, Real, STEP>:
             d2[1][e] = d2[0][e] * a.tw[2 * p];
         }
         Ff::template run<2>(d2, t, tl, lds);
-        cx<Real>* y = a.w2 + k2;  // output k1 = 2m + chain
+        cx<Real>* y = a.w2;  // output k1 = 2m + chain
 #pragma unroll
         for (int e = 0; e < C::E; ++e)
             if (live) {
                 const long m = Ff::out_pos(t, e);
-                gst(y + w2row(i0, 2 * m), d2[0][e]);
-                gst(y + w2row(i0, 2 * m + 1), d2[1][e]);
+                gst(y + w2at(i0, 2 * m, k2), d2[0][e]);
+                gst(y + w2at(i0, 2 * m + 1, k2), d2[1][e]);
             }
     } else if constexpr (STEP == 3) {
         // B divides hw, and 2 n1 hw lines are whole workgroups: a workgroup
-        // holds one k1 and one aligned k2 tile, every lane addresses W2 and K
-        // inside their rows (lanes past k2 = n2 work on the padding), and the
-        // addresses are a workgroup-uniform base per element plus one 32-bit
-        // lane offset.  The axis length n0 is the compile-time FL.
+        // holds one k1 and B columns of one aligned k2 tile, every lane
+        // addresses W2 and K inside their rows (lanes past k2 = n2 work on the
+        // padding), and the addresses are a workgroup-uniform base per element
+        // plus one 32-bit lane offset.  The axis length n0 is the compile-time
+        // FL.  Consecutive groups take consecutive k1 of one tile and k1 block
+        // (then the tiles, then the blocks): their W2 pieces share lines.
         constexpr int N0 = FL;
-        const long line0 = grp * B;
-        const long k1 = line0 / hw, k2b = line0 % hw;
+        long g = grp;
+        const long sub = g % (KT / B);
+        g /= KT / B;
+        const long k1r = g % kb;
+        g /= kb;
+        const long tiles = hw / KT;
+        const long k1 = (g / tiles) * kb + k1r, k2b = (g % tiles) * KT + sub * B;
         const uint32_t s0 = uint32_t(kb) * uint32_t(hw);  // i0 stride
-        cx<Real>* const xu = a.w2 + w2row(0, k1) + k2b;
+        cx<Real>* const xu = a.w2 + w2at(0, k1, k2b);
         const uint32_t xl = (uint32_t(c) + uint32_t(t) * s0) * uint32_t(sizeof(cx<Real>));
         const uint32_t wl = uint32_t(2 * t) * uint32_t(sizeof(cx<Real>));
         cx<Real> w[C::E];  // w^p of each input position p = t + in_pos(0, e)
@@ -204,7 +217,6 @@ __global__ void __launch_bounds__((GCfg<L, Real, STEP>::B * GCfg<L, Real, STEP>:
         // at the folded index min(k0, 2 n0 - k0); the folded k0 steps by
         // kGTile.  An element whose k0 all lie on one side of n0 is a uniform
         // base plus the lane offset 2t or -2t (written as 2 (T - 1 - t)).
-        constexpr int KT = psn_host::kGTile;
         const int k1f = int(k1 <= n1 ? k1 : 2 * n1 - k1);
         const Real* const Ku = a.K + psn_host::g_k_index(N0, n2, 0, k1f, int(k2b));
         const uint32_t kup = (uint32_t(2 * KT) * uint32_t(t) + uint32_t(c)) * uint32_t(sizeof(Real));
@@ -232,12 +244,12 @@ __global__ void __launch_bounds__((GCfg<L, Real, STEP>::B * GCfg<L, Real, STEP>:
             gst(byte_off(sbase(xu + size_t(Ff::in_pos(0, e)) * s0), xl), twfma<+1>(d2[1][e], w[e], d2[0][e]));
     } else if constexpr (STEP == 4) {
         const long i0 = ln / hw, k2 = ln % hw;
-        const cx<Real>* x = a.w2 + k2;  // input k1 = 2m + chain
+        const cx<Real>* x = a.w2;  // input k1 = 2m + chain
 #pragma unroll
         for (int e = 0; e < C::E; ++e) {
             const long m = Fi::in_pos(t, e);
-            d2[0][e] = live ? gld(x + w2row(i0, 2 * m)) : cx<Real>{Real(0), Real(0)};
-            d2[1][e] = live ? gld(x + w2row(i0, 2 * m + 1)) : cx<Real>{Real(0), Real(0)};
+            d2[0][e] = live ? gld(x + w2at(i0, 2 * m, k2)) : cx<Real>{Real(0), Real(0)};
+            d2[1][e] = live ? gld(x + w2at(i0, 2 * m + 1, k2)) : cx<Real>{Real(0), Real(0)};
         }
         Fi::template run<2>(d2, t, tl, lds);
         cx<Real>* y = a.w1 + i0 * n1 * hw + k2;
