@@ -196,7 +196,10 @@ __global__ void __launch_bounds__((GCfg<L, Real, STEP>::B * GCfg<L, Real, STEP>:
             // workgroup is partial), not from the lane's own line
             const long i0w = grp * B / hw, k2w = grp * B % hw;
             const int run = kb * B;
-            for (int q = 2 * int(threadIdx.x); q < 2 * FL * B; q += 2 * B * T) {
+            constexpr int NQ = FL / T;  // stores per lane: 2 FL B elements, two per lane and store
+#pragma unroll
+            for (int r = 0; r < NQ; ++r) {
+                const int q = 2 * int(threadIdx.x) + r * 2 * B * T;
                 cx<Real>* y = a.w2 + w2at(i0w, long(q / run) * kb, k2w) + q % run;
                 if constexpr (sizeof(Real) == 4) {
                     gst2(y, sb[q], sb[q + 1]);
@@ -294,19 +297,24 @@ __global__ void __launch_bounds__((GCfg<L, Real, STEP>::B * GCfg<L, Real, STEP>:
         // inverse of length FL of Y[k] = (X[k] + conj X[FL-k])
         // + i (X[k] - conj X[FL-k]) w^-k gives z_j = u_2j + i u_2j+1; only
         // j < FL/2 lies inside the box.
+        // Each X[k] is loaded once, into the line's LDS row (X[FL] by its
+        // first thread), and the partner X[FL-k] read back from there.
         using Fh = TeamFFT<FL, T, Real, +1, false>;
         const cx<Real>* x = a.w1 + ln * hw;
 #pragma unroll
+        for (int e = 0; e < C::E; ++e) d[e] = live ? gld(x + Fh::in_pos(t, e)) : cx<Real>{Real(0), Real(0)};
+        const cx<Real> last = (live && t == 0) ? gld(x + FL) : cx<Real>{Real(0), Real(0)};
+#pragma unroll
+        for (int e = 0; e < C::E; ++e) lds.put(Fh::in_pos(t, e), d[e]);
+        if (t == 0) lds.put(FL, last);
+        __syncthreads();
+#pragma unroll
         for (int e = 0; e < C::E; ++e) {
             const int k = Fh::in_pos(t, e);
-            cx<Real> v{Real(0), Real(0)};
-            if (live) {
-                const cx<Real> p = gld(x + k), q = conj(gld(x + (FL - k)));
-                v = (p + q) + rot<+1>(mul_conj(p - q, tl(k)));
-            }
-            d[e] = v;
+            const cx<Real> p = d[e], q = conj(lds.get(FL - k));
+            d[e] = (p + q) + rot<+1>(mul_conj(p - q, tl(k)));
         }
-        Fh::run1(d, t, tl, lds);
+        Fh::run1(d, t, tl, lds);  // its first exchange waits before reusing the row
         Io* y = a.u + ln * n2;
 #pragma unroll
         for (int e = 0; e < C::E; ++e) {
