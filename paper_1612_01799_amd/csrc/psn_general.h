@@ -98,7 +98,6 @@ __global__ void __launch_bounds__((GCfg<L, Real, STEP>::B * GCfg<L, Real, STEP>:
     const int h = n2 + 1;                 // k2 of the spectrum
     const long hw = psn_host::g_pitch(n2);  // elements per workspace row
     const int kb = a.kb;
-    // offset of W2 row (i0, k1)
     // offset of W2 element (i0, k1, k2)
     constexpr long KT = psn_host::kGTile;
     auto w2at = [&](long i0, long k1, long k2) {
