@@ -1,6 +1,6 @@
 // Grids with a different number of points per axis (paper section 2's
 // general box, N = n0 n1 n2 points, section 3): the same convolution, run as
-// five line-transform steps over plain workspaces.  Each step transforms
+// five line-transform steps over their own workspaces.  Each step transforms
 // lines of one axis at that axis' padded length L = 2 n_q, with the zero half
 // of the input formed in registers and only the needed outputs stored:
 //
