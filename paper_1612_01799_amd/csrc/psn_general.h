@@ -67,7 +67,17 @@ struct GCfg {
     static constexpr int E = elems_per_thread(FL, rows ? int(sizeof(Real)) : 8);
     static constexpr int T = FL / E;
     static constexpr int CX = sizeof(cx<Real>);
-    static constexpr int TWS = TwLds<Real>::slots(FL);
+    // The axis-0 step at n0 >= 512 reads its stage twiddles from per-stage
+    // rows (one row per thread and stage, as P3 does at those sizes), the
+    // other steps from the swizzled table.
+    static constexpr bool trows = STEP == 3 && FL >= 512;
+    using Ff = TeamFFT<FL, T, Real, -1, false>;
+    using Fi = TeamFFT<FL, T, Real, +1, STEP == 3>;
+    static constexpr int tw_slots() {
+        if constexpr (trows) return Ff::rows_size() + (Ff::template same_rows<Fi>() ? 0 : Fi::rows_size());
+        else return TwLds<Real>::slots(FL);
+    }
+    static constexpr int TWS = tw_slots();
     static constexpr int pitch() {
         int np = FL + (FL >> 4) + 1;
         while (np % 32 != 8) ++np;
@@ -119,9 +129,17 @@ __global__ void __launch_bounds__((GCfg<L, Real, STEP>::B * GCfg<L, Real, STEP>:
     // join every barrier
     [[maybe_unused]] const bool live = line < nlines && (rows || line % hw < h);
     [[maybe_unused]] const long ln = live ? line : 0;
-    // the length-FL table from every other entry of the step's length-L table
+    // the length-FL table from every other entry of the step's length-L
+    // table, or the twiddle rows of both transforms (taken from the same)
     TwLds<Real> tl{sb + B * C::NP};
-    for (int i = threadIdx.x; i < L; i += B * T) tl.p[TwLds<Real>::at(i)] = a.tw[2 * i];
+    cx<Real>* const rows_f = sb + B * C::NP;
+    cx<Real>* const rows_i = rows_f + (Ff::template same_rows<Fi>() ? 0 : Ff::rows_size());
+    if constexpr (C::trows) {
+        Ff::template fill_rows<1, 2>(rows_f, a.tw, threadIdx.x, B * T);
+        if constexpr (!Ff::template same_rows<Fi>()) Fi::template fill_rows<1, 2>(rows_i, a.tw, threadIdx.x, B * T);
+    } else {
+        for (int i = threadIdx.x; i < L; i += B * T) tl.p[TwLds<Real>::at(i)] = a.tw[2 * i];
+    }
     __syncthreads();
     using View = std::conditional_t<rows, LdsRows<Real>, LdsCols2<Real>>;
     View lds = [&] {
@@ -245,7 +263,8 @@ __global__ void __launch_bounds__((GCfg<L, Real, STEP>::B * GCfg<L, Real, STEP>:
             d2[0][e] = gld(byte_off(sbase(xu + size_t(p0) * s0), xl));
             d2[1][e] = d2[0][e] * w[e];
         }
-        Ff::template run<2>(d2, t, tl, lds);
+        if constexpr (C::trows) Ff::template run<2>(d2, t, TwRows<Real>{rows_f}, lds);
+        else Ff::template run<2>(d2, t, tl, lds);
         // kernel values of the outputs k0 = 2m + chain, m = t + out_pos(0, e),
         // at the folded index min(k0, 2 n0 - k0); the folded k0 steps by
         // kGTile.  An element whose k0 all lie on one side of n0 is a uniform
@@ -271,7 +290,8 @@ __global__ void __launch_bounds__((GCfg<L, Real, STEP>::B * GCfg<L, Real, STEP>:
             }
         // radices reversed: starts from the forward output layout and ends in
         // its input layout (slot e at position Ff::in_pos(t, e))
-        Fi::template run_scaled<2>(d2, t, tl, lds, kk);
+        if constexpr (C::trows) Fi::template run_scaled<2>(d2, t, TwRows<Real>{rows_i}, lds, kk);
+        else Fi::template run_scaled<2>(d2, t, tl, lds, kk);
 #pragma unroll
         for (int e = 0; e < C::E; ++e)
             gst(byte_off(sbase(xu + size_t(Ff::in_pos(0, e)) * s0), xl), twfma<+1>(d2[1][e], w[e], d2[0][e]));
