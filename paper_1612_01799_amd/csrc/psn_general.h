@@ -83,7 +83,13 @@ struct GCfg {
         while (np % 32 != 8) ++np;
         return np;
     }
-    static constexpr int NP = rows ? pitch() : 2 * FL;  // LDS elements per line
+    // The FP32 axis-0 step at n0 >= 512 exchanges its two chains one after
+    // the other through a one-chain area (two more barriers per exchange) and
+    // asks the compiler for six waves per SIMD (at most 80 VGPRs), so that
+    // three workgroups share a CU.
+    static constexpr bool seq = STEP == 3 && sizeof(Real) == 4 && FL >= 512;
+    static constexpr int min_waves = seq ? 6 : 1;
+    static constexpr int NP = rows ? pitch() : seq ? FL : 2 * FL;  // LDS elements per line
     static constexpr int pick() {
         for (int b = psn_host::kGTile; b > 1; b /= 2)
             if ((b * NP + TWS) * CX <= (rows ? 65536 : 163840) && b * T <= 1024) return b;
@@ -95,7 +101,8 @@ struct GCfg {
 };
 
 template <int L, class Real, class Io, int STEP>
-__global__ void __launch_bounds__((GCfg<L, Real, STEP>::B * GCfg<L, Real, STEP>::T)) g_step(const GArgs<Real, Io> a) {
+__global__ void __launch_bounds__((GCfg<L, Real, STEP>::B * GCfg<L, Real, STEP>::T), (GCfg<L, Real, STEP>::min_waves))
+    g_step(const GArgs<Real, Io> a) {
     using C = GCfg<L, Real, STEP>;
     constexpr int B = C::B, T = C::T;
     constexpr bool rows = STEP == 1 || STEP == 5;
@@ -141,9 +148,10 @@ __global__ void __launch_bounds__((GCfg<L, Real, STEP>::B * GCfg<L, Real, STEP>:
         for (int i = threadIdx.x; i < L; i += B * T) tl.p[TwLds<Real>::at(i)] = a.tw[2 * i];
     }
     __syncthreads();
-    using View = std::conditional_t<rows, LdsRows<Real>, LdsCols2<Real>>;
+    using View = std::conditional_t<rows, LdsRows<Real>, std::conditional_t<C::seq, LdsColsSeq<Real>, LdsCols2<Real>>>;
     View lds = [&] {
         if constexpr (rows) return LdsRows<Real>{sb + c * C::NP};
+        else if constexpr (C::seq) return LdsColsSeq<Real>{sb, B, c};
         else return LdsCols2<Real>{sb, B, c};
     }();
     cx<Real> d[C::E];          // the row steps' line
