@@ -83,11 +83,12 @@ struct GCfg {
         while (np % 32 != 8) ++np;
         return np;
     }
-    // The FP32 axis-0 step at n0 >= 512 exchanges its two chains one after
-    // the other through a one-chain area (two more barriers per exchange) and
-    // asks the compiler for six waves per SIMD (at most 80 VGPRs), so that
-    // three workgroups share a CU.
-    static constexpr bool seq = STEP == 3 && sizeof(Real) == 4 && FL >= 512;
+    // The FP32 axis-0 step and axis-1 inverse step at n_q >= 512 exchange
+    // their two chains one after the other through a one-chain area (two more
+    // barriers per exchange) and ask the compiler for six waves per SIMD (at
+    // most 80 VGPRs), so that three workgroups share a CU.  (The forward
+    // axis-1 step keeps both chains: its staged stores need the whole area.)
+    static constexpr bool seq = (STEP == 3 || STEP == 4) && sizeof(Real) == 4 && FL >= 512;
     static constexpr int min_waves = seq ? 6 : 1;
     static constexpr int NP = rows ? pitch() : seq ? FL : 2 * FL;  // LDS elements per line
     static constexpr int pick() {
