@@ -83,13 +83,14 @@ struct GCfg {
         while (np % 32 != 8) ++np;
         return np;
     }
-    // The FP32 axis-0 step and axis-1 inverse step at n_q >= 512 exchange
-    // their two chains one after the other through a one-chain area (two more
-    // barriers per exchange) and ask the compiler for six waves per SIMD (at
-    // most 80 VGPRs), so that three workgroups share a CU.  (The forward
-    // axis-1 step keeps both chains: its staged stores need the whole area.)
-    static constexpr bool seq = (STEP == 3 || STEP == 4) && sizeof(Real) == 4 && FL >= 512;
-    static constexpr int min_waves = seq ? 6 : 1;
+    // The FP32 axis-0 step and axis-1 inverse step exchange their two chains
+    // one after the other through a one-chain area (two more barriers per
+    // exchange), so that more workgroups share a CU; at n_q >= 512 they ask the
+    // compiler for six waves per SIMD (at most 80 VGPRs: three workgroups).
+    // (The forward axis-1 step keeps both chains: its staged stores need the
+    // whole area.)
+    static constexpr bool seq = (STEP == 3 || STEP == 4) && sizeof(Real) == 4;
+    static constexpr int min_waves = seq && FL >= 512 ? 6 : 1;
     static constexpr int NP = rows ? pitch() : seq ? FL : 2 * FL;  // LDS elements per line
     static constexpr int pick() {
         for (int b = psn_host::kGTile; b > 1; b /= 2)
