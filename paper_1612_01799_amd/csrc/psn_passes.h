@@ -1059,9 +1059,12 @@ template <int N, int DT>
 struct CorrCfg {
     using Real = typename Prec<DT>::Real;
     static constexpr int E = elems_per_thread(N, sizeof(Real));
-    static constexpr int T = N / E;
+    static constexpr int T = N / E;  // axis 2
+    // axes 0 and 1: at most 8 elements per thread (FP32 otherwise takes 16),
+    // so that the three workgroups that fit a CU's LDS hold twice the waves
+    static constexpr int T01 = N / elems_per_thread(N, 8);
     static constexpr int CX = sizeof(cx<Real>);
-    static constexpr int B = (N % 8 == 0 && (8 * N + TwLds<Real>::slots(N)) * CX <= 65536 && 8 * T <= 1024) ? 8
+    static constexpr int B = (N % 8 == 0 && (8 * N + TwLds<Real>::slots(N)) * CX <= 65536 && 8 * T01 <= 1024) ? 8
                              : (N % 4 == 0 && (4 * N + TwLds<Real>::slots(N)) * CX <= 65536) ? 4
                                                                                               : 1;
     static constexpr int LC = pick_lines(N, T, CX, 256, kMaxLds);  // axis-2 lines
@@ -1072,13 +1075,13 @@ template <int N, int DT, int AX, int DIR>
 __global__ void corr_fft(const CorrBatch<DT> cb) {
     using CC = CorrCfg<N, DT>;
     using Real = typename CC::Real;
-    using F = TeamFFT<N, CC::T, Real, DIR, false>;
     extern __shared__ __align__(16) unsigned char smem[];
     cx<Real>* sb = reinterpret_cast<cx<Real>*>(smem);
     const CorrProb<DT>& P = cb.p[blockIdx.y];
     cx<Real>* __restrict__ z = P.z;
-    cx<Real> d[F::E];
     if constexpr (AX == 2) {
+        using F = TeamFFT<N, CC::T, Real, DIR, false>;
+        cx<Real> d[F::E];
         using Io = typename Prec<DT>::Io;
         const int t = threadIdx.x % CC::T, ln = threadIdx.x / CC::T;
         const size_t base = (size_t(blockIdx.x) * CC::LC + ln) * N;
@@ -1102,14 +1105,21 @@ __global__ void corr_fft(const CorrBatch<DT> cb) {
             }
         }
     } else {
-        constexpr int B = CC::B;
+        constexpr int B = CC::B, TT = CC::T01;
+        using F = TeamFFT<N, TT, Real, DIR, false>;
+        cx<Real> d[F::E];
+        // units (line, tile of B columns), tiles fastest, dealt XCD-aware so
+        // that neighbouring tiles (which share 128-byte lines) meet in one L2
+        constexpr int units = N * (N / B);
+        const int u = xcd_unit();
+        if (u >= units) return;  // whole workgroup
         const int c = threadIdx.x % B, t = threadIdx.x / B;
-        const int line = blockIdx.x / (N / B), i2 = (blockIdx.x % (N / B)) * B + c;
+        const int line = u / (N / B), i2 = (u % (N / B)) * B + c;
         // axis 1: (i0 = line, pos, i2); axis 0: (pos, i1 = line, i2)
         const size_t stride = AX == 1 ? size_t(N) : size_t(N) * N;
         const size_t base = (AX == 1 ? size_t(line) * N * N : size_t(line) * N) + i2;
         TwLds<Real> tl{sb + B * N};
-        tl.fill(P.tw, N, threadIdx.x, B * CC::T);
+        tl.fill(P.tw, N, threadIdx.x, B * TT);
         __syncthreads();
 #pragma unroll
         for (int e = 0; e < F::E; ++e) d[e] = gld(z + base + size_t(F::in_pos(t, e)) * stride);
@@ -1118,7 +1128,7 @@ __global__ void corr_fft(const CorrBatch<DT> cb) {
         if constexpr (AX == 0) {
             // z *= (C0 - (C2/6) |kappa|^2) / n^3 at (k0, k1 = line, k2 = i2), then the
             // inverse with the radices reversed, which starts from this layout
-            using Fi = TeamFFT<N, CC::T, Real, +1, true>;
+            using Fi = TeamFFT<N, TT, Real, +1, true>;
             auto kap2 = [](double kq, int k) {
                 const double v = kq * double(k <= N / 2 ? k : k - N);
                 return v * v;
@@ -1141,6 +1151,13 @@ __global__ void corr_fft(const CorrBatch<DT> cb) {
     }
 }
 
+// ------------------------------------------------------------------ launcher
+// Kernels needing more than 64 KB of dynamic LDS must say so once.
+inline bool allow_lds(const void* fn, size_t bytes) {
+    if (bytes <= 65536) return true;
+    return hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, int(bytes)) == hipSuccess;
+}
+
 // The correction's passes before the solve's axis-2 pass (z after the
 // axis-1 inverse) and the one after it (axis-2 inverse added to u).
 template <int N, int DT>
@@ -1148,8 +1165,8 @@ hipError_t launch_corr_z(const CorrBatch<DT>& cb, hipStream_t s) {
     using CC = CorrCfg<N, DT>;
     const size_t lds2 = (size_t(CC::LC) * CC::NP + TwLds<typename CC::Real>::slots(N)) * CC::CX;
     const size_t lds01 = (size_t(CC::B) * N + TwLds<typename CC::Real>::slots(N)) * CC::CX;
-    const dim3 g2(N * N / CC::LC, cb.count), g01(N * (N / CC::B), cb.count);
-    const dim3 b2(CC::LC * CC::T), b01(CC::B * CC::T);
+    const dim3 g2(N * N / CC::LC, cb.count), g01(xcd_grid(N * (N / CC::B)), cb.count);
+    const dim3 b2(CC::LC * CC::T), b01(CC::B * CC::T01);
     hipLaunchKernelGGL((corr_fft<N, DT, 2, -1>), g2, b2, lds2, s, cb);
     hipLaunchKernelGGL((corr_fft<N, DT, 1, -1>), g01, b01, lds01, s, cb);
     hipLaunchKernelGGL((corr_fft<N, DT, 0, -1>), g01, b01, lds01, s, cb);
@@ -1162,13 +1179,6 @@ hipError_t launch_corr_add(const CorrBatch<DT>& cb, hipStream_t s) {
     const size_t lds2 = (size_t(CC::LC) * CC::NP + TwLds<typename CC::Real>::slots(N)) * CC::CX;
     hipLaunchKernelGGL((corr_fft<N, DT, 2, +1>), dim3(N * N / CC::LC, cb.count), dim3(CC::LC * CC::T), lds2, s, cb);
     return hipGetLastError();
-}
-
-// ------------------------------------------------------------------ launcher
-// Kernels needing more than 64 KB of dynamic LDS must say so once.
-inline bool allow_lds(const void* fn, size_t bytes) {
-    if (bytes <= 65536) return true;
-    return hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, int(bytes)) == hipSuccess;
 }
 
 // ------------------------------------------------------------------ schedules
