@@ -1048,27 +1048,32 @@ struct CorrBatch {
     CorrProb<DT> p[kMaxBatch];
 };
 
-// Length-N transforms of z along axis AX (DIR = -1 forward, +1 inverse,
-// unnormalised).  Axis 2: a workgroup holds LC contiguous lines, one LDS row
-// each; the forward reads rho (real) instead of z, the inverse adds the real
-// part of its result to u instead of storing z.  Axes 0 and 1: a workgroup
-// holds B adjacent lines (consecutive i2), element-major in LDS, so each
-// point's B values are one contiguous run; on axis 0 the forward is followed
-// in registers by the symbol and the inverse (DIR is ignored there).
+// Length-N transforms of the real density along each axis (DIR = -1
+// forward, +1 inverse, unnormalised), on its half spectrum z[i0][i1][k2],
+// k2 = 0..N/2, rows padded to HZ.  Axis 2: a workgroup holds LC contiguous
+// lines, one LDS row each; the forward reads a row of rho as N/2 complex
+// pairs, transforms them at length N/2 and unpacks the N/2 + 1 outputs (as
+// P1), the inverse packs them back and adds the row to u (as P5).  Axes 0
+// and 1: a workgroup holds B adjacent lines (consecutive k2), element-major
+// in LDS, so each point's B values are one contiguous run; on axis 0 the
+// forward is followed in registers by the symbol and the inverse (DIR is
+// ignored there).
 template <int N, int DT>
 struct CorrCfg {
     using Real = typename Prec<DT>::Real;
-    static constexpr int E = elems_per_thread(N, sizeof(Real));
-    static constexpr int T = N / E;  // axis 2
+    static constexpr int CX = sizeof(cx<Real>);
+    // axis 2: packed transforms of length N/2
+    static constexpr int E = elems_per_thread(N / 2, sizeof(Real));
+    static constexpr int T = N / 2 / E;
+    static constexpr int LC = pick_lines(N / 2, T, CX, 256, kMaxLds);  // axis-2 lines
+    static constexpr int NP = rows_padded(N / 2);
     // axes 0 and 1: at most 8 elements per thread (FP32 otherwise takes 16),
     // so that the three workgroups that fit a CU's LDS hold twice the waves
     static constexpr int T01 = N / elems_per_thread(N, 8);
-    static constexpr int CX = sizeof(cx<Real>);
     static constexpr int B = (N % 8 == 0 && (8 * N + TwLds<Real>::slots(N)) * CX <= 65536 && 8 * T01 <= 1024) ? 8
                              : (N % 4 == 0 && (4 * N + TwLds<Real>::slots(N)) * CX <= 65536) ? 4
                                                                                               : 1;
-    static constexpr int LC = pick_lines(N, T, CX, 256, kMaxLds);  // axis-2 lines
-    static constexpr int NP = Cfg<N, DT>::NP;
+    static constexpr int HZ = (N / 2 + B) / B * B;  // N/2 + 1 rounded up to B
 };
 
 template <int N, int DT, int AX, int DIR>
@@ -1080,44 +1085,91 @@ __global__ void corr_fft(const CorrBatch<DT> cb) {
     const CorrProb<DT>& P = cb.p[blockIdx.y];
     cx<Real>* __restrict__ z = P.z;
     if constexpr (AX == 2) {
-        using F = TeamFFT<N, CC::T, Real, DIR, false>;
+        // packed length FL = N/2: z_j = x_2j + i x_2j+1, Z = DFT_FL(z),
+        // X[k] = (Z[k] + conj Z[FL-k])/2 + w^k (Z[k] - conj Z[FL-k])/(2i),
+        // w = exp(-2 pi i / N), X[0] and X[FL] from Z[0]; the inverse packs
+        // Y[k] = (X[k] + conj X[FL-k]) + i w^-k (X[k] - conj X[FL-k]) and
+        // IDFT_FL(Y)_j = u_2j + i u_2j+1
+        constexpr int FL = N / 2;
+        using F = TeamFFT<FL, CC::T, Real, DIR, false>;
         cx<Real> d[F::E];
         using Io = typename Prec<DT>::Io;
         const int t = threadIdx.x % CC::T, ln = threadIdx.x / CC::T;
-        const size_t base = (size_t(blockIdx.x) * CC::LC + ln) * N;
+        const size_t line = size_t(blockIdx.x) * CC::LC + ln;
+        const size_t base = line * N;  // of rho and u
+        cx<Real>* const zr = z + line * CC::HZ;
+        // the length-FL table exp(-2 pi i m / N), m < N: every other entry of
+        // the plan's length-2N table
         TwLds<Real> tl{sb + CC::LC * CC::NP};
-        tl.fill(P.tw, N, threadIdx.x, CC::LC * CC::T);
+        for (int i = threadIdx.x; i < N; i += CC::LC * CC::T) tl.p[TwLds<Real>::at(i)] = P.tw[2 * i];
         __syncthreads();
-#pragma unroll
-        for (int e = 0; e < F::E; ++e) {
-            if constexpr (DIR < 0) d[e] = {Real(P.rho[base + F::in_pos(t, e)]), Real(0)};
-            else d[e] = gld(z + base + F::in_pos(t, e));
-        }
         LdsRows<Real> lds{sb + ln * CC::NP};
-        F::run1(d, t, tl, lds);
+        if constexpr (DIR < 0) {
 #pragma unroll
-        for (int e = 0; e < F::E; ++e) {
-            if constexpr (DIR < 0) {
-                gst(z + base + F::out_pos(t, e), d[e]);
-            } else {
-                Io* __restrict__ u = P.u + base + F::out_pos(t, e);
-                *u = Io(*u + Io(d[e].x));
+            for (int e = 0; e < F::E; ++e) {
+                const int j = F::in_pos(t, e);
+                d[e] = {Real(P.rho[base + 2 * j]), Real(P.rho[base + 2 * j + 1])};
+            }
+            F::run1(d, t, tl, lds);
+            __syncthreads();  // the transform's last exchange reads are done
+#pragma unroll
+            for (int e = 0; e < F::E; ++e) lds.put(F::out_pos(t, e), d[e]);
+            __syncthreads();
+#pragma unroll
+            for (int e = 0; e < F::E; ++e) {
+                const int k = F::out_pos(t, e);
+                const cx<Real> Z = lds.get(k);
+                if (k == 0) {
+                    gst(zr, cx<Real>{Z.x + Z.y, Real(0)});
+                    gst(zr + FL, cx<Real>{Z.x - Z.y, Real(0)});
+                } else {
+                    const cx<Real> Zr = conj(lds.get(FL - k));
+                    const cx<Real> Ev = scale(Z + Zr, Real(0.5));
+                    const cx<Real> Od = rot<-1>(scale(Z - Zr, Real(0.5)));
+                    gst(zr + k, Ev + Od * tl(k));
+                }
+            }
+        } else {
+            // each X[k] loaded once into the line's row (X[FL] by its first
+            // thread); the partner X[FL-k] read back from there
+#pragma unroll
+            for (int e = 0; e < F::E; ++e) d[e] = gld(zr + F::in_pos(t, e));
+            const cx<Real> last = t == 0 ? gld(zr + FL) : cx<Real>{Real(0), Real(0)};
+#pragma unroll
+            for (int e = 0; e < F::E; ++e) lds.put(F::in_pos(t, e), d[e]);
+            if (t == 0) lds.put(FL, last);
+            __syncthreads();
+#pragma unroll
+            for (int e = 0; e < F::E; ++e) {
+                const int k = F::in_pos(t, e);
+                const cx<Real> p = d[e], q = conj(lds.get(FL - k));
+                d[e] = (p + q) + rot<+1>(mul_conj(p - q, tl(k)));
+            }
+            F::run1(d, t, tl, lds);  // its first exchange waits before reusing the row
+#pragma unroll
+            for (int e = 0; e < F::E; ++e) {
+                const int j = F::out_pos(t, e);
+                Io* __restrict__ u = P.u + base + 2 * j;
+                u[0] = Io(u[0] + Io(d[e].x));
+                u[1] = Io(u[1] + Io(d[e].y));
             }
         }
     } else {
         constexpr int B = CC::B, TT = CC::T01;
         using F = TeamFFT<N, TT, Real, DIR, false>;
         cx<Real> d[F::E];
-        // units (line, tile of B columns), tiles fastest, dealt XCD-aware so
-        // that neighbouring tiles (which share 128-byte lines) meet in one L2
-        constexpr int units = N * (N / B);
+        // units (line, tile of B columns k2), tiles fastest, dealt XCD-aware
+        // so that neighbouring tiles (which share 128-byte lines) meet in one
+        // L2; columns past k2 = N/2 transform the row padding
+        constexpr int HZ = CC::HZ;
+        constexpr int units = N * (HZ / B);
         const int u = xcd_unit();
         if (u >= units) return;  // whole workgroup
         const int c = threadIdx.x % B, t = threadIdx.x / B;
-        const int line = u / (N / B), i2 = (u % (N / B)) * B + c;
-        // axis 1: (i0 = line, pos, i2); axis 0: (pos, i1 = line, i2)
-        const size_t stride = AX == 1 ? size_t(N) : size_t(N) * N;
-        const size_t base = (AX == 1 ? size_t(line) * N * N : size_t(line) * N) + i2;
+        const int line = u / (HZ / B), i2 = (u % (HZ / B)) * B + c;
+        // axis 1: (i0 = line, pos, k2 = i2); axis 0: (pos, i1 = line, k2 = i2)
+        const size_t stride = AX == 1 ? size_t(HZ) : size_t(N) * HZ;
+        const size_t base = (AX == 1 ? size_t(line) * N * HZ : size_t(line) * HZ) + i2;
         TwLds<Real> tl{sb + B * N};
         tl.fill(P.tw, N, threadIdx.x, B * TT);
         __syncthreads();
@@ -1163,9 +1215,9 @@ inline bool allow_lds(const void* fn, size_t bytes) {
 template <int N, int DT>
 hipError_t launch_corr_z(const CorrBatch<DT>& cb, hipStream_t s) {
     using CC = CorrCfg<N, DT>;
-    const size_t lds2 = (size_t(CC::LC) * CC::NP + TwLds<typename CC::Real>::slots(N)) * CC::CX;
+    const size_t lds2 = (size_t(CC::LC) * CC::NP + TwLds<typename CC::Real>::slots(N / 2)) * CC::CX;
     const size_t lds01 = (size_t(CC::B) * N + TwLds<typename CC::Real>::slots(N)) * CC::CX;
-    const dim3 g2(N * N / CC::LC, cb.count), g01(xcd_grid(N * (N / CC::B)), cb.count);
+    const dim3 g2(N * N / CC::LC, cb.count), g01(xcd_grid(N * (CC::HZ / CC::B)), cb.count);
     const dim3 b2(CC::LC * CC::T), b01(CC::B * CC::T01);
     hipLaunchKernelGGL((corr_fft<N, DT, 2, -1>), g2, b2, lds2, s, cb);
     hipLaunchKernelGGL((corr_fft<N, DT, 1, -1>), g01, b01, lds01, s, cb);
@@ -1176,7 +1228,7 @@ hipError_t launch_corr_z(const CorrBatch<DT>& cb, hipStream_t s) {
 template <int N, int DT>
 hipError_t launch_corr_add(const CorrBatch<DT>& cb, hipStream_t s) {
     using CC = CorrCfg<N, DT>;
-    const size_t lds2 = (size_t(CC::LC) * CC::NP + TwLds<typename CC::Real>::slots(N)) * CC::CX;
+    const size_t lds2 = (size_t(CC::LC) * CC::NP + TwLds<typename CC::Real>::slots(N / 2)) * CC::CX;
     hipLaunchKernelGGL((corr_fft<N, DT, 2, +1>), dim3(N * N / CC::LC, cb.count), dim3(CC::LC * CC::T), lds2, s, cb);
     return hipGetLastError();
 }

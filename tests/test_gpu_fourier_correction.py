@@ -27,7 +27,7 @@ def _solve(torch, plan, rho_np, inplace=False):
     return u.double().cpu().numpy()
 
 
-@pytest.mark.parametrize("n", [16, 24, 48, 64, 96, 128])
+@pytest.mark.parametrize("n", [8, 12, 16, 24, 48, 64, 96, 128, 160, 162])
 @pytest.mark.parametrize("dtype", ["f64", "f32", "split"])
 def test_fourier_correction_matches_oracle(n, dtype):
     torch = torch_cuda()
