@@ -98,7 +98,7 @@ struct GCfg {
         return 1;
     }
     static constexpr int B = pick();
-    static_assert(psn_host::kGTile % B == 0, "a strided workgroup lies inside one k2 tile");
+    static_assert(rows || B == psn_host::kGTile, "a strided workgroup is one whole k2 tile");
     static constexpr size_t lds = size_t(B * NP + TWS) * CX;
 };
 
@@ -203,47 +203,35 @@ __global__ void __launch_bounds__((GCfg<L, Real, STEP>::B * GCfg<L, Real, STEP>:
             d2[1][e] = d2[0][e] * a.tw[2 * p];
         }
         Ff::template run<2>(d2, t, tl, lds);
-        // output k1 = 2m + chain
-        if constexpr (B == KT) {
-            // The workgroup's 2 n1 x B outputs are one tile of W2 in each of
-            // the 2 n1 / KB k1 blocks, each a run of KB B elements.  Stage them
-            // in LDS in k1-major order (the two-chain exchange area holds
-            // exactly 2 n1 B values), then store the runs, two elements per
-            // lane (lanes of padding lines store padding).
-            __syncthreads();  // the transform's last exchange reads are done
+        // output k1 = 2m + chain.  The workgroup's 2 n1 x B outputs are one
+        // tile of W2 in each of the 2 n1 / KB k1 blocks, each a run of KB B
+        // elements.  Stage them in LDS in k1-major order (the two-chain
+        // exchange area holds exactly 2 n1 B values), then store the runs, two
+        // elements per lane (lanes of padding lines store padding).
+        __syncthreads();  // the transform's last exchange reads are done
 #pragma unroll
-            for (int e = 0; e < C::E; ++e) {
-                const int m = Ff::out_pos(t, e);
-                sb[(2 * m) * B + c] = d2[0][e];
-                sb[(2 * m + 1) * B + c] = d2[1][e];
+        for (int e = 0; e < C::E; ++e) {
+            const int m = Ff::out_pos(t, e);
+            sb[(2 * m) * B + c] = d2[0][e];
+            sb[(2 * m + 1) * B + c] = d2[1][e];
+        }
+        __syncthreads();
+        // every lane stores for the whole workgroup: its i0 and tile come
+        // from the workgroup's first line (B divides hw, and no workgroup is
+        // partial), not from the lane's own line
+        const long i0w = grp * B / hw, k2w = grp * B % hw;
+        const int run = kb * B;
+        constexpr int NQ = FL / T;  // stores per lane: 2 FL B elements, two per lane and store
+#pragma unroll
+        for (int r = 0; r < NQ; ++r) {
+            const int q = 2 * int(threadIdx.x) + r * 2 * B * T;
+            cx<Real>* y = a.w2 + w2at(i0w, long(q / run) * kb, k2w) + q % run;
+            if constexpr (sizeof(Real) == 4) {
+                gst2(y, sb[q], sb[q + 1]);
+            } else {
+                gst(y, sb[q]);
+                gst(y + 1, sb[q + 1]);
             }
-            __syncthreads();
-            // every lane stores for the whole workgroup: its i0 and tile
-            // come from the workgroup's first line (B divides hw, and no
-            // workgroup is partial), not from the lane's own line
-            const long i0w = grp * B / hw, k2w = grp * B % hw;
-            const int run = kb * B;
-            constexpr int NQ = FL / T;  // stores per lane: 2 FL B elements, two per lane and store
-#pragma unroll
-            for (int r = 0; r < NQ; ++r) {
-                const int q = 2 * int(threadIdx.x) + r * 2 * B * T;
-                cx<Real>* y = a.w2 + w2at(i0w, long(q / run) * kb, k2w) + q % run;
-                if constexpr (sizeof(Real) == 4) {
-                    gst2(y, sb[q], sb[q + 1]);
-                } else {
-                    gst(y, sb[q]);
-                    gst(y + 1, sb[q + 1]);
-                }
-            }
-        } else {
-            cx<Real>* y = a.w2;
-#pragma unroll
-            for (int e = 0; e < C::E; ++e)
-                if (live) {
-                    const long m = Ff::out_pos(t, e);
-                    gst(y + w2at(i0, 2 * m, k2), d2[0][e]);
-                    gst(y + w2at(i0, 2 * m + 1, k2), d2[1][e]);
-                }
         }
     } else if constexpr (STEP == 3) {
         // B divides hw, and 2 n1 hw lines are whole workgroups: a workgroup
