@@ -67,3 +67,25 @@ def test_noalloc_batch_refuses_oversize_workspace():
     psn.solve_batched_noalloc([plan] * 2, rhos[:2], outs[:2])  # 2 x 98 MB fits
     torch.cuda.synchronize()
     assert all(bool((o == 0).all()) for o in outs[:2])
+
+
+def test_noalloc_batch_with_fourier_correction():
+    """Plans that add the correction by the Fourier series keep its half
+    spectrum in the workspace too: the same outputs as the allocating entry
+    point, and the oracle's paper-form solve, on two calls in a row."""
+    torch = torch_cuda()
+    for n, L, seed in ((48, 2.5, 11), (24, 2.0, 12)):
+        box = W.Box.cube(L, n)
+        mix = W.draw_mixture(seed, 4, -L / 4, L / 4, 0.15 * L, 0.3 * L, 0.5, 1.5, box)
+        r = W.mixture_density(mix)
+        plans = [psn.Plan(n, L, 1e-12, "f32", correction="fourier").build(), psn.Plan(n, L, 1e-12, "f32").build()]
+        rho = torch.from_numpy(r).to("cuda", torch.float32)
+        print(f"no-alloc batch with the Fourier-series correction: n={n}", flush=True)
+        ref_out = psn.solve_batched(plans, [rho, rho])
+        outs = [torch.full_like(rho, float("nan")) for _ in plans]
+        psn.solve_batched_noalloc(plans, [rho, rho], outs)
+        torch.cuda.synchronize()
+        for a, b in zip(outs, ref_out):
+            assert torch.equal(a, b), n
+        assert max_rel(outs[0].double().cpu().numpy(), O.solve_paper_form(r, box, 1e-12)) <= TOL["f32"]
+        assert max_rel(outs[1].double().cpu().numpy(), O.solve(r, oracle_symbol(n, L))) <= TOL["f32"]
