@@ -50,10 +50,11 @@ struct GArgs {
 // DFT(x w^p), w = exp(-2 pi i / L); the inverse that keeps the first n_q
 // outputs is IDFT(even) + w^-p IDFT(odd).  The two chains of a line advance in
 // lockstep through one LDS exchange.
-// B lines per workgroup: up to kGTile (a divisor of it), within the 160 KB of
-// LDS for the strided steps (64-byte FP32 row pieces; two workgroups of eight
-// length-512 lines share a CU, which measured faster than one of sixteen) and
-// within 64 KB for the row steps, where more lines only cost occupancy.
+// B lines per workgroup: for the strided steps kGTile, within the 160 KB of
+// LDS (64-byte FP32 row pieces; two workgroups of eight length-512 lines
+// share a CU, which measured faster than one of sixteen); for the row steps
+// up to 16 and 512 threads within 80 KB, so that two workgroups share a CU
+// and each fills its twiddle table for twice the rows (as P1/P5).
 // The row steps keep each line as an LDS row of pitch NP (threads of a team
 // walk along it; the skew of one slot per 16 and a pitch of 8 mod 32 spread a
 // wave's accesses over the banks); the strided steps keep the lines as columns
@@ -93,8 +94,13 @@ struct GCfg {
     static constexpr int min_waves = seq && FL >= 512 ? 6 : 1;
     static constexpr int NP = rows ? pitch() : seq ? FL : 2 * FL;  // LDS elements per line
     static constexpr int pick() {
-        for (int b = psn_host::kGTile; b > 1; b /= 2)
-            if ((b * NP + TWS) * CX <= (rows ? 65536 : 163840) && b * T <= 1024) return b;
+        if constexpr (rows) {
+            for (int b = 16; b > 1; b /= 2)
+                if ((b * NP + TWS) * CX <= 81920 && b * T <= 512) return b;
+        } else {
+            for (int b = psn_host::kGTile; b > 1; b /= 2)
+                if ((b * NP + TWS) * CX <= 163840 && b * T <= 1024) return b;
+        }
         return 1;
     }
     static constexpr int B = pick();
