@@ -84,13 +84,11 @@ struct GCfg {
         while (np % 32 != 8) ++np;
         return np;
     }
-    // The FP32 axis-0 step and axis-1 inverse step exchange their two chains
-    // one after the other through a one-chain area (two more barriers per
-    // exchange), so that more workgroups share a CU; at n_q >= 512 they ask the
-    // compiler for six waves per SIMD (at most 80 VGPRs: three workgroups).
-    // (The forward axis-1 step keeps both chains: its staged stores need the
-    // whole area.)
-    static constexpr bool seq = (STEP == 3 || STEP == 4) && sizeof(Real) == 4;
+    // The FP32 strided steps exchange their two chains one after the other
+    // through a one-chain area (two more barriers per exchange), so that more
+    // workgroups share a CU; at n_q >= 512 they ask the compiler for six waves
+    // per SIMD (at most 80 VGPRs: three workgroups).
+    static constexpr bool seq = STEP >= 2 && STEP <= 4 && sizeof(Real) == 4;
     static constexpr int min_waves = seq && FL >= 512 ? 6 : 1;
     static constexpr int NP = rows ? pitch() : seq ? FL : 2 * FL;  // LDS elements per line
     static constexpr int pick() {
@@ -211,32 +209,42 @@ __global__ void __launch_bounds__((GCfg<L, Real, STEP>::B * GCfg<L, Real, STEP>:
         Ff::template run<2>(d2, t, tl, lds);
         // output k1 = 2m + chain.  The workgroup's 2 n1 x B outputs are one
         // tile of W2 in each of the 2 n1 / KB k1 blocks, each a run of KB B
-        // elements.  Stage them in LDS in k1-major order (the two-chain
-        // exchange area holds exactly 2 n1 B values), then store the runs, two
-        // elements per lane (lanes of padding lines store padding).
-        __syncthreads();  // the transform's last exchange reads are done
-#pragma unroll
-        for (int e = 0; e < C::E; ++e) {
-            const int m = Ff::out_pos(t, e);
-            sb[(2 * m) * B + c] = d2[0][e];
-            sb[(2 * m + 1) * B + c] = d2[1][e];
-        }
-        __syncthreads();
-        // every lane stores for the whole workgroup: its i0 and tile come
-        // from the workgroup's first line (B divides hw, and no workgroup is
-        // partial), not from the lane's own line
+        // elements.  Stage them in LDS in k1-major order, then store the runs,
+        // two elements per lane (lanes of padding lines store padding).  The
+        // exchange area holds R of the 2 n1 B values: one round with both
+        // chains' area, two with the one-chain area (k1 < n1, then k1 >= n1).
+        // Every lane stores for the whole workgroup: its i0 and tile come from
+        // the workgroup's first line (B divides hw, and no workgroup is
+        // partial), not from the lane's own line.
         const long i0w = grp * B / hw, k2w = grp * B % hw;
         const int run = kb * B;
-        constexpr int NQ = FL / T;  // stores per lane: 2 FL B elements, two per lane and store
+        constexpr int rounds = C::seq ? 2 : 1;
+        constexpr int K1R = 2 * FL / rounds;  // k1 per round
+        constexpr int NQ = K1R / (2 * T);     // stores per lane and round, two elements each
 #pragma unroll
-        for (int r = 0; r < NQ; ++r) {
-            const int q = 2 * int(threadIdx.x) + r * 2 * B * T;
-            cx<Real>* y = a.w2 + w2at(i0w, long(q / run) * kb, k2w) + q % run;
-            if constexpr (sizeof(Real) == 4) {
-                gst2(y, sb[q], sb[q + 1]);
-            } else {
-                gst(y, sb[q]);
-                gst(y + 1, sb[q + 1]);
+        for (int h = 0; h < rounds; ++h) {
+            __syncthreads();  // the transform's last exchange (or the last round's stores) read the area
+#pragma unroll
+            for (int e = 0; e < C::E; ++e) {
+                const int m = Ff::out_pos(t, e);
+#pragma unroll
+                for (int ch = 0; ch < 2; ++ch) {
+                    const int k1 = 2 * m + ch - h * K1R;
+                    if (k1 >= 0 && k1 < K1R) sb[k1 * B + c] = d2[ch][e];
+                }
+            }
+            __syncthreads();
+#pragma unroll
+            for (int r = 0; r < NQ; ++r) {
+                const int q = 2 * int(threadIdx.x) + r * 2 * B * T;  // in this round's area
+                const int qg = h * K1R * B + q;                         // among the 2 n1 B outputs
+                cx<Real>* y = a.w2 + w2at(i0w, long(qg / run) * kb, k2w) + qg % run;
+                if constexpr (sizeof(Real) == 4) {
+                    gst2(y, sb[q], sb[q + 1]);
+                } else {
+                    gst(y, sb[q]);
+                    gst(y + 1, sb[q + 1]);
+                }
             }
         }
     } else if constexpr (STEP == 3) {
