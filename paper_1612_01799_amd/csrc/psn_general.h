@@ -253,16 +253,16 @@ __global__ void __launch_bounds__((GCfg<L, Real, STEP>::B * GCfg<L, Real, STEP>:
         // addresses W2 and K inside their rows (lanes past k2 = n2 work on the
         // padding), and the addresses are a workgroup-uniform base per element
         // plus one 32-bit lane offset.  The axis length n0 is the compile-time
-        // FL.  Consecutive groups take consecutive k1 of one tile and k1 block
-        // (then the tiles, then the blocks): their W2 pieces share lines.
+        // FL.  Consecutive groups of one tile take k1 = 0, 2 n1 - 1, 1,
+        // 2 n1 - 2, ...: each pair k1, 2 n1 - k1 shares a kernel row, and k1,
+        // k1 + 1 (two groups apart) share the lines of their W2 pieces.
         constexpr int N0 = FL;
         long g = grp;
         const long sub = g % (KT / B);
         g /= KT / B;
-        const long k1r = g % kb;
-        g /= kb;
-        const long tiles = hw / KT;
-        const long k1 = (g / tiles) * kb + k1r, k2b = (g % tiles) * KT + sub * B;
+        const long q = g % (2L * n1);
+        const long k1 = q % 2 == 0 ? q / 2 : 2L * n1 - (q + 1) / 2;
+        const long k2b = (g / (2L * n1)) * KT + sub * B;
         const uint32_t s0 = uint32_t(kb) * uint32_t(hw);  // i0 stride
         cx<Real>* const xu = a.w2 + w2at(0, k1, k2b);
         const uint32_t xl = (uint32_t(c) + uint32_t(t) * s0) * uint32_t(sizeof(cx<Real>));
