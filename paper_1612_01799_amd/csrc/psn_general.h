@@ -86,10 +86,12 @@ struct GCfg {
     }
     // The strided steps exchange their two chains one after the other
     // through a one-chain area (two more barriers per exchange), so that more
-    // workgroups share a CU; in FP32 at n_q >= 512 they ask the compiler for
-    // six waves per SIMD (at most 80 VGPRs: three workgroups).
+    // workgroups share a CU; at n_q >= 512 they ask the compiler for six
+    // waves per SIMD in FP32 (at most 80 VGPRs: three workgroups) and four in
+    // FP64 arithmetic (at most 128 VGPRs: two workgroups; the axis-0 step then
+    // spills a few registers and still runs about 5 % faster).
     static constexpr bool seq = STEP >= 2 && STEP <= 4;
-    static constexpr int min_waves = seq && sizeof(Real) == 4 && FL >= 512 ? 6 : 1;
+    static constexpr int min_waves = seq && FL >= 512 ? (sizeof(Real) == 4 ? 6 : 4) : 1;
     static constexpr int NP = rows ? pitch() : seq ? FL : 2 * FL;  // LDS elements per line
     static constexpr int pick() {
         if constexpr (rows) {
