@@ -40,7 +40,8 @@ struct GArgs {
     const Real* K;
     const cx<Real>* tw;  // exp(-2 pi i m / 2L), m < 2L, for this step's length L
     int n0, n1, n2;
-    int kb;  // k1 block of W2
+    int kb;   // k1 block of W2 (a power of two)
+    int kbs;  // log2 kb
 };
 
 // Every step runs transforms of length FL = L/2 = n_q.  The axis-2 steps
@@ -122,11 +123,11 @@ __global__ void __launch_bounds__((GCfg<L, Real, STEP>::B * GCfg<L, Real, STEP>:
     const int n0 = a.n0, n1 = a.n1, n2 = a.n2;
     const int h = n2 + 1;                 // k2 of the spectrum
     const long hw = psn_host::g_pitch(n2);  // elements per workspace row
-    const int kb = a.kb;
+    const int kb = a.kb, kbs = a.kbs;
     // offset of W2 element (i0, k1, k2)
     constexpr long KT = psn_host::kGTile;
     auto w2at = [&](long i0, long k1, long k2) {
-        return (((k1 / kb) * n0 + i0) * (hw / KT) + k2 / KT) * (kb * KT) + (k1 % kb) * KT + k2 % KT;
+        return (((k1 >> kbs) * n0 + i0) * (hw / KT) + k2 / KT) * (kb * KT) + (k1 & (kb - 1)) * KT + k2 % KT;
     };
     const int c = rows ? int(threadIdx.x) / T : int(threadIdx.x) % B;
     const int t = rows ? int(threadIdx.x) % T : int(threadIdx.x) / B;
@@ -240,7 +241,7 @@ __global__ void __launch_bounds__((GCfg<L, Real, STEP>::B * GCfg<L, Real, STEP>:
             for (int r = 0; r < NQ; ++r) {
                 const int q = 2 * int(threadIdx.x) + r * 2 * B * T;  // in this round's area
                 const int qg = h * K1R * B + q;                         // among the 2 n1 B outputs
-                cx<Real>* y = a.w2 + w2at(i0w, long(qg / run) * kb, k2w) + qg % run;
+                cx<Real>* y = a.w2 + w2at(i0w, long(qg >> (kbs + __builtin_ctz(B))) * kb, k2w) + (qg & (run - 1));
                 if constexpr (sizeof(Real) == 4) {
                     gst2(y, sb[q], sb[q + 1]);
                 } else {

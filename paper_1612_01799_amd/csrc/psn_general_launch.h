@@ -12,7 +12,8 @@ hipError_t general_solve(const psn_host::Slot& sl, hipStream_t s, hipEvent_t* ev
     const int n0 = p->ng[0], n1 = p->ng[1], n2 = p->ng[2];
     GArgs<Real, Io> a{static_cast<const Io*>(sl.rho), static_cast<Io*>(sl.u), static_cast<cx<Real>*>(sl.W1),
                       static_cast<cx<Real>*>(sl.W2), static_cast<const Real*>(p->K), nullptr, n0, n1, n2,
-                      psn_host::w2_k1_block(n1)};
+                      psn_host::w2_k1_block(n1), 0};
+    while ((1 << a.kbs) < a.kb) ++a.kbs;
     // twiddle tables exp(-2 pi i m / 4 n_q), m < 4 n_q, one after the other
     const cx<Real>* tw = static_cast<const cx<Real>*>(p->tw);
     const cx<Real>* tw0 = tw;
